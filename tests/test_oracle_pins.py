@@ -55,6 +55,18 @@ def test_sph_harm_orthonormal_on_quadrature_grid():
     assert np.abs(G - np.eye(L * L)).max() < 1e-13
 
 
+def test_gauss_legendre_rule_is_exact_to_rounding():
+    """Legendre polynomials up to degree n-1 are orthogonal under the n-node rule; numpy's
+    own rule misses this by ~3e-13 at n = 91, the polished one must not."""
+    from oracle.slsht import gauss_legendre
+    for n in (91, 200):
+        x, w = gauss_legendre(n)
+        lam = legendre_table(n - 1, np.arccos(x))
+        G = np.einsum("lt,kt,t->lk", lam[:, 0], lam[:, 0], w) * 2 * np.pi
+        assert np.abs(G - np.eye(n)).max() < 5e-14
+        assert abs(w.sum() - 2.0) < 1e-15
+
+
 # --------------------------------------------------------------------------------------
 # Wigner-d / Wigner-D (Section II-B, factoring of rotations in Section IV-B)
 
