@@ -1,0 +1,197 @@
+/*
+ * slsht.h -- C ABI of the MI355X (gfx950) directional SLSHT library.
+ *
+ * The directional spatially localized spherical harmonic transform of
+ * Khalid, Kennedy, Durrani, Sadeghi, Wiaux and McEwen (IEEE Trans. Signal
+ * Processing, 2013) maps a band-limited signal f on the sphere and an
+ * asymmetric band-limited window h to the distribution
+ *
+ *     g(rho; l, m) = int_{S^2} f(x) (D_rho h)(x) conj(Y_l^m(x)) ds(x)
+ *
+ * (Definition 1, eq. Eq:stft_spatial) for rotations rho = (phi, theta, omega)
+ * = (alpha, beta, gamma) on an SO(3) grid and spectral indices (l, m).
+ *
+ * The library evaluates it in separated form: Wigner-3j coupling of f into
+ * A^p_q(l, m) = conj((conj(f) Y_l^m)_p^q)  (eqs. Eq:harmonic_formulation and
+ * Eq:alternative_harmonic_formulation), then, per (l, m), the contraction with
+ * h and Wigner-d(theta) over p, and pruned Fourier synthesis over omega and phi
+ * (eq. Eq:alternative_harmonic_formulation_wigner with the separation-of-
+ * variables remark of Section IV-B).
+ *
+ * Conventions used by every entry point:
+ *  - Band-limits are exclusive: f_l^m = 0 for l >= L_f, h_s^r = 0 for s >= L_h.
+ *    g(.; l, m) vanishes for l >= L_f + L_h - 1 (remark after
+ *    Eq:harmonic_formulation).
+ *  - Coefficient arrays (f, h, f_out) are complex double, interleaved
+ *    (re, im), at flat index l*l + l + m.
+ *  - Spherical harmonics carry the Condon-Shortley phase; Wigner-D is
+ *    D^l_{m,m'}(alpha,beta,gamma) = e^{-i m alpha} d^l_{m,m'}(beta) e^{-i m' gamma}
+ *    (eq. Eq:Dlm); rotations are zyz (Section II-B).
+ *  - SO(3) grid (Section II-D, definition of E_L, with per-axis sizes):
+ *    phi_a = 2 pi a / n_phi, theta_b = 2 pi b / n_phi (b < n_theta =
+ *    (n_phi + 1) / 2, n_phi odd), omega_c = 2 pi c / n_omega.
+ *  - Output index of (l, m): lm = l*l + l + m - l_lo*l_lo.
+ *    FULL output:   g[lm][c][b - theta_lo][a]  (phi contiguous), complex128
+ *                   (SLSHT_FP64) or complex64 (SLSHT_FP32_MIXED).
+ *    ENERGY output: E[l - l_lo][c][b - theta_lo][a] = sum_{|m|<=l} |g|^2,
+ *                   double (SLSHT_FP64) or float (SLSHT_FP32_MIXED).
+ *  - Device pointers are HIP device memory owned by the caller; the library
+ *    never frees them and keeps no reference after a call returns.  A
+ *    `stream` argument is a hipStream_t (NULL = the default stream); work is
+ *    enqueued asynchronously on it.
+ *  - Every function returns an slsht_status; nothing throws across the ABI.
+ *    Argument checks run on the host before any launch.  The message of the
+ *    last failure on the calling thread is available from slsht_last_error().
+ */
+#ifndef SLSHT_H
+#define SLSHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLSHT_OK = 0,
+    SLSHT_EINVAL = -1,     /* bad argument or descriptor                        */
+    SLSHT_ENOMEM = -2,     /* device or host allocation failed                  */
+    SLSHT_EDEVICE = -3,    /* HIP runtime / kernel launch error                 */
+    SLSHT_EBUSY = -4,      /* serving: no capacity right now, retry later       */
+    SLSHT_ENOTFOUND = -5,  /* serving: unknown ticket                           */
+    SLSHT_ETOOBIG = -6     /* serving: request can never fit the HBM budget     */
+} slsht_status;
+
+enum { SLSHT_FP64 = 0, SLSHT_FP32_MIXED = 1 };      /* slsht_desc.precision   */
+enum { SLSHT_OUT_FULL = 0, SLSHT_OUT_ENERGY = 1 };  /* slsht_desc.output_mode */
+/* slsht_desc.flags: f and h are real-signal consistent (c_l^{-m} =
+ * (-1)^m conj(c_l^m)), so g(rho; l, -m) = (-1)^m conj(g(rho; l, m))
+ * (last remark of Section IV-B); the library then synthesises m >= 0 only.   */
+enum { SLSHT_REAL_PAIR = 1u };
+
+#define SLSHT_MAX_LH 32        /* largest supported window band-limit L_h     */
+#define SLSHT_MAX_LF 2048      /* largest supported signal band-limit L_f     */
+#define SLSHT_MAX_NPHI 2047    /* largest supported n_phi                     */
+
+/* Problem statement (Definition 1; Section IV-A for the grid). */
+typedef struct {
+    int32_t L_f;          /* signal band-limit, 1 <= L_f <= SLSHT_MAX_LF            */
+    int32_t L_h;          /* window band-limit, 1 <= L_h <= SLSHT_MAX_LH            */
+    int32_t l_lo, l_hi;   /* output degrees l_lo <= l < l_hi <= L_f + L_h - 1       */
+    int32_t n_phi;        /* odd, 1 <= n_phi <= SLSHT_MAX_NPHI                      */
+    int32_t n_theta;      /* must equal (n_phi + 1) / 2                             */
+    int32_t n_omega;      /* >= 1                                                   */
+    int32_t precision;    /* SLSHT_FP64 or SLSHT_FP32_MIXED                         */
+    int32_t output_mode;  /* SLSHT_OUT_FULL or SLSHT_OUT_ENERGY                     */
+    uint32_t flags;       /* 0 or SLSHT_REAL_PAIR                                   */
+    int32_t theta_lo;     /* first theta row computed, 0 <= theta_lo < theta_hi     */
+    int32_t theta_hi;     /* one past the last row; 0 means n_theta                 */
+} slsht_desc;
+
+typedef struct slsht_plan_s* slsht_plan_t;
+typedef struct slsht_server_s* slsht_server_t;
+
+/* Message of the last failure on the calling thread ("" if none). The pointer
+ * stays valid until the next library call on this thread. */
+const char* slsht_last_error(void);
+
+/* Host-only check of a descriptor against the rules above.  Needs no GPU. */
+int slsht_validate(const slsht_desc* desc);
+
+/* Host-only byte counts for a descriptor: device memory a plan holds
+ * (Wigner-d table, twiddles, beta weights, coupling scratch), the output
+ * buffer slsht_forward writes, and per-call scratch.  Any pointer may be NULL.
+ * Needs no GPU. */
+int slsht_footprint(const slsht_desc* desc, size_t* plan_bytes, size_t* out_bytes,
+                    size_t* scratch_bytes);
+
+/* Number of complex coefficients of the coupling output for a descriptor:
+ * (l_hi^2 - l_lo^2) * L_h^2.  Needs no GPU. */
+int64_t slsht_coupling_size(const slsht_desc* desc);
+
+/* Build a plan on `device`: validates desc, computes the Wigner-d(theta_b)
+ * table d^p_{q,q'}(theta_b) for p < L_h, |q|,|q'| <= p (Section II-B,
+ * eq. Eq:Dlm) on the GPU in FP64 by the three-term recursion in p (stored in
+ * FP32 for SLSHT_FP32_MIXED), the phi and omega twiddles, and the beta weights
+ * q(theta_b) of the discrete inverse (Section IV-A).  The plan owns that memory
+ * and a coupling scratch of slsht_coupling_size() complex doubles.  Forward,
+ * coupling and inverse calls on one plan share that scratch: issue them on one
+ * stream, or use one plan per stream.  Synchronises the device before return. */
+int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out);
+int slsht_plan_destroy(slsht_plan_t plan);
+/* Copy of the descriptor a plan was built from. */
+int slsht_plan_desc(slsht_plan_t plan, slsht_desc* out);
+
+/* Forward transform (Definition 1, evaluated as described at the top):
+ *   f: device, complex128[L_f * L_f]      signal coefficients f_l^m
+ *   h: device, complex128[L_h * L_h]      window coefficients h_s^r
+ *   g: device, FULL or ENERGY layout above, caller-allocated, at least
+ *      out_bytes of slsht_footprint()
+ * With SLSHT_REAL_PAIR set, f and h must be real-signal consistent (not
+ * checked); m < 0 outputs are then written from m > 0 by the conjugate
+ * symmetry.  Asynchronous on `stream`. */
+int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void* stream);
+
+/* Coupling stage alone: A[lm][p*p + p + q] = sum_{l'} f_{l'}^{m-q} T(l', m-q; p, q; l, m)
+ * = int f Y_p^q conj(Y_l^m) ds, the coefficient that multiplies
+ * h_p^{q'} D^p_{q,q'}(rho) in Eq:harmonic_formulation (it equals
+ * conj((conj(f) Y_l^m)_p^q) of Eq:alternative_harmonic_formulation).
+ *   f: device complex128[L_f * L_f];  A: device complex128[slsht_coupling_size()].
+ * Useful to analyse several windows against one signal (remark on multiple
+ * windows, Section IV-B).  Asynchronous on `stream`. */
+int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream);
+
+/* Inverse through the spectral marginal (Section III-C): for every (l, m) of the
+ * plan,  f_hat = (1/(n_phi^2 n_omega)) sum_{a,b,c} q(theta_b) g(phi_a, theta_b, omega_c; l, m)
+ * (eq. Eq:sig_reconstruction_discrete with per-axis sizes), and
+ * f_out[lm] = f_hat / (sqrt(16 pi^3) h_0^0)  (eq. Eq:inversion_2).  The result is
+ * f_l^m for l < L_f and zero (to rounding) for l >= L_f.
+ *   g: device, FULL layout of this plan;  h: device complex128[L_h * L_h] (only
+ *   h_0^0 is read, on the host, with a synchronous 16-byte copy);
+ *   f_out: device complex128[l_hi^2 - l_lo^2].
+ * Requires a FULL plan over all theta rows with n_phi, n_omega >= 2 L_h - 1,
+ * and h_0^0 != 0 (SLSHT_EINVAL otherwise).  Asynchronous after the h_0^0 read. */
+int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of forward transforms of uneven size.
+ *
+ * A server owns one worker thread, device plans cached by descriptor, and an
+ * HBM budget for request outputs and inputs.  Requests are admitted in arrival
+ * order as budget frees up; every admitted request's kernels are enqueued at
+ * once on the server's streams, so transforms of different requests overlap
+ * on the device.  Results stay in server-owned device memory until released.
+ */
+enum { SLSHT_REQ_QUEUED = 0, SLSHT_REQ_RUNNING = 1, SLSHT_REQ_DONE = 2, SLSHT_REQ_FAILED = 3 };
+
+/* hbm_budget: bytes of device memory the server may hold for request inputs and
+ * outputs together; n_streams: device streams used for concurrent requests (1..8). */
+int slsht_server_create(int device, size_t hbm_budget, int n_streams, slsht_server_t* out);
+/* Waits for in-flight work, then frees every buffer, plan and stream. */
+int slsht_server_destroy(slsht_server_t server);
+/* Copies f (complex128[L_f^2]) and h (complex128[L_h^2]) from host memory and
+ * queues the request; returns a ticket.  SLSHT_ETOOBIG if the request alone
+ * exceeds the budget, SLSHT_EINVAL for a bad descriptor. */
+int slsht_submit(slsht_server_t server, const slsht_desc* desc, const void* f_host,
+                 const void* h_host, uint64_t* ticket);
+/* Non-blocking state query.  When DONE, *g_dev is the device output (layout of
+ * slsht_forward) and *out_bytes its size; when FAILED, *err holds the status. */
+int slsht_poll(slsht_server_t server, uint64_t ticket, int* state, const void** g_dev,
+               size_t* out_bytes, int* err);
+/* Blocks until the request is DONE or FAILED (or timeout_ms elapses: EBUSY). */
+int slsht_wait(slsht_server_t server, uint64_t ticket, int timeout_ms);
+/* Returns a finished request's output memory to the budget. */
+int slsht_release(slsht_server_t server, uint64_t ticket);
+/* Timestamps (seconds on the server's monotonic clock) of a finished request:
+ * submit, admission (enqueue) and completion.  Any pointer may be NULL. */
+int slsht_request_times(slsht_server_t server, uint64_t ticket, double* t_submit,
+                        double* t_start, double* t_done);
+/* Current server clock (same origin as slsht_request_times). */
+double slsht_server_clock(slsht_server_t server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLSHT_H */

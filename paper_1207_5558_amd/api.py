@@ -1,0 +1,141 @@
+"""PyTorch-facing wrapper of the C ABI.
+
+PyTorch supplies device memory and streams; the transform itself runs in the
+library's kernels.  Coefficient tensors are complex128 at flat index
+l*l + l + m (exclusive band-limits); output layouts are those of slsht.h.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp64": L.SLSHT_FP64, "fp32": L.SLSHT_FP32_MIXED}
+_MODE = {"full": L.SLSHT_OUT_FULL, "energy": L.SLSHT_OUT_ENERGY}
+
+
+def make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, precision="fp64", output="full",
+              real_pair=False, theta_lo=0, theta_hi=0) -> L.Desc:
+    return L.Desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, _PREC[precision],
+                  _MODE[output], L.SLSHT_REAL_PAIR if real_pair else 0, theta_lo, theta_hi)
+
+
+def desc_for(wl, **over) -> L.Desc:
+    """Descriptor of a workload from paper_1207_5558_amd.inputs."""
+    kw = dict(precision=wl.precision, output=wl.output)
+    kw.update(over)
+    return make_desc(wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta, wl.n_omega, **kw)
+
+
+def validate(desc: L.Desc) -> None:
+    L.check(L.lib().slsht_validate(ctypes.byref(desc)))
+
+
+def footprint(desc: L.Desc) -> tuple[int, int, int]:
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    L.check(L.lib().slsht_footprint(ctypes.byref(desc), ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype, numel, name) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Device plan for one descriptor (Wigner-d table, twiddles, weights)."""
+
+    def __init__(self, desc: L.Desc, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        self.desc = L.Desc.from_buffer_copy(desc)
+        h = ctypes.c_void_p()
+        L.check(L.lib().slsht_plan(ctypes.byref(self.desc), device, ctypes.byref(h)))
+        self._h = h
+        d = self.desc
+        self.n_theta_out = (d.theta_hi or d.n_theta) - d.theta_lo
+        self.n_lm = d.l_hi * d.l_hi - d.l_lo * d.l_lo
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            L.check(L.lib().slsht_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def output_shape(self) -> tuple[int, ...]:
+        d = self.desc
+        lead = self.n_lm if d.output_mode == L.SLSHT_OUT_FULL else d.l_hi - d.l_lo
+        return (lead, d.n_omega, self.n_theta_out, d.n_phi)
+
+    @property
+    def output_dtype(self):
+        d = self.desc
+        if d.output_mode == L.SLSHT_OUT_FULL:
+            return torch.complex128 if d.precision == L.SLSHT_FP64 else torch.complex64
+        return torch.float64 if d.precision == L.SLSHT_FP64 else torch.float32
+
+    def empty_output(self) -> torch.Tensor:
+        return torch.empty(self.output_shape, dtype=self.output_dtype,
+                           device=f"cuda:{self.device}")
+
+    def forward(self, f: torch.Tensor, h: torch.Tensor, g: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+        d = self.desc
+        if g is None:
+            g = self.empty_output()
+        pf = _dev_ptr(f, torch.complex128, d.L_f * d.L_f, "f")
+        ph = _dev_ptr(h, torch.complex128, d.L_h * d.L_h, "h")
+        n_out = 1
+        for s in self.output_shape:
+            n_out *= s
+        pg = _dev_ptr(g, self.output_dtype, n_out, "g")
+        L.check(L.lib().slsht_forward(self._h, pf, ph, pg, _stream_handle(stream)))
+        return g
+
+    def coupling(self, f: torch.Tensor, A: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        d = self.desc
+        n = self.n_lm * d.L_h * d.L_h
+        if A is None:
+            A = torch.empty((self.n_lm, d.L_h * d.L_h), dtype=torch.complex128,
+                            device=f"cuda:{self.device}")
+        L.check(L.lib().slsht_coupling(self._h, _dev_ptr(f, torch.complex128, d.L_f * d.L_f, "f"),
+                                       _dev_ptr(A, torch.complex128, n, "A"),
+                                       _stream_handle(stream)))
+        return A
+
+    def inverse(self, g: torch.Tensor, h: torch.Tensor, f_out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+        d = self.desc
+        if f_out is None:
+            f_out = torch.empty(self.n_lm, dtype=torch.complex128, device=f"cuda:{self.device}")
+        n_out = 1
+        for s in self.output_shape:
+            n_out *= s
+        L.check(L.lib().slsht_inverse(self._h, _dev_ptr(g, self.output_dtype, n_out, "g"),
+                                      _dev_ptr(h, torch.complex128, d.L_h * d.L_h, "h"),
+                                      _dev_ptr(f_out, torch.complex128, self.n_lm, "f_out"),
+                                      _stream_handle(stream)))
+        return f_out

@@ -1,0 +1,584 @@
+// gfx950 kernels of the directional SLSHT forward path and its inverse.
+//
+// Separated form of the distribution (eq. Eq:alternative_harmonic_formulation_wigner,
+// evaluated by separation of variables as noted in Section IV-B):
+//
+//   g(phi_a, theta_b, omega_c; l, m)
+//     = sum_q e^{-i q phi_a} sum_{q'} e^{-i q' omega_c}
+//       sum_{p >= max(|q|,|q'|)} A^p_q(l,m) h_p^{q'} d^p_{q,q'}(theta_b)
+//
+// with A^p_q(l,m) = sum_{l'} f_{l'}^{m-q} T(l', m-q; p, q; l, m) the Wigner-3j
+// coupling of f (Eq:harmonic_formulation).  Kernels:
+//   K1 wigner_table_kernel  d^p_{q,q'}(theta_b), FP64 recursion in p
+//   K2 coupling_kernel      A^p_q(l,m), FP64 two-sided 3j recursions
+//   K3 synth_full_kernel    theta-contraction, omega- and phi-synthesis, store
+//   K4 inverse_kernel       weighted sum over the grid (Section IV-A)
+#include "slsht_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+namespace slsht {
+
+// ------------------------------------------------------------------------------
+// small complex helpers (interleaved re, im in HIP vector types)
+
+template <typename T> struct VecOf;
+template <> struct VecOf<double> { using type = double2; };
+template <> struct VecOf<float> { using type = float2; };
+
+template <typename V> __device__ __forceinline__ V vmk(decltype(V::x) x, decltype(V::x) y) {
+    V v; v.x = x; v.y = y; return v;
+}
+template <typename V> __device__ __forceinline__ V vadd(V a, V b) { return vmk<V>(a.x + b.x, a.y + b.y); }
+template <typename V> __device__ __forceinline__ V vsub(V a, V b) { return vmk<V>(a.x - b.x, a.y - b.y); }
+// -i * v
+template <typename V> __device__ __forceinline__ V vmul_mi(V v) { return vmk<V>(v.y, -v.x); }
+template <typename V> __device__ __forceinline__ V vcast(double2 a) {
+    return vmk<V>((decltype(V::x))a.x, (decltype(V::x))a.y);
+}
+
+// ------------------------------------------------------------------------------
+// K1: Wigner-d table.  One thread per (theta row, q, q'); the thread seeds
+// d^{p0}_{q,q'} at p0 = max(|q|,|q'|) from the one-term form of Wigner's sum
+// and climbs in p with the three-term recursion
+//   p sqrt(((p+1)^2-q^2)((p+1)^2-q'^2)) d^{p+1}
+//     = (2p+1)(p(p+1) cos(beta) - q q') d^p - (p+1) sqrt((p^2-q^2)(p^2-q'^2)) d^{p-1},
+// all in FP64; consecutive threads hold consecutive q', so each degree's row
+// segment is written contiguously.  beta = 2 pi b / n_phi (grid E_L, Section II-D).
+
+__device__ __forceinline__ double ipow(double x, int n) {
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+template <typename OutT>
+__global__ void wigner_table_kernel(OutT* __restrict__ tab, int L, int n_phi, int theta_lo,
+                                    int n_rows, int64_t row_len) {
+    const int K = 2 * L - 1;
+    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    if (pair >= K * K || row >= n_rows) return;
+    const int q = pair / K - (L - 1);
+    const int qp = pair % K - (L - 1);
+    const int b = theta_lo + row;
+    double sh, ch;                       // sin(beta/2), cos(beta/2), beta/2 = pi b / n_phi
+    sincospi((double)b / (double)n_phi, &sh, &ch);
+    const double cb = cospi(2.0 * (double)b / (double)n_phi);
+
+    const int aq = q < 0 ? -q : q, aqp = qp < 0 ? -qp : qp;
+    const int j0 = aq > aqp ? aq : aqp;
+    // Seed: d^j_{r,cc}(beta) for r = +-j, by the single surviving term of
+    // Wigner's sum; d^j_{q,q'} = (-1)^{q-q'} d^j_{q',q} covers |q'| > |q|.
+    int r, cc;
+    double sg = 1.0;
+    if (aq >= aqp) { r = q; cc = qp; }
+    else { r = qp; cc = q; sg = ((q - qp) & 1) ? -1.0 : 1.0; }
+    double bin = 1.0;                    // C(2j, j - cc)
+    for (int i = 1; i <= j0 - cc; ++i) bin *= (double)(j0 + cc + i) / (double)i;
+    double d = sqrt(bin) * sg;
+    if (r == j0) d *= ipow(ch, j0 + cc) * ipow(-sh, j0 - cc);
+    else         d *= ipow(ch, j0 - cc) * ipow(sh, j0 + cc);
+
+    OutT* out = tab + (int64_t)row * row_len;
+    double dprev = 0.0;
+    const double qq = (double)q * (double)qp;
+    for (int p = j0; p < L; ++p) {
+        out[dtab_off(p) + (q + p) * (2 * p + 1) + (qp + p)] = (OutT)d;
+        if (p + 1 >= L) break;
+        double dn;
+        if (p == 0) {
+            dn = cb;                     // d^1_{00} = cos(beta); the recursion divides by p
+        } else {
+            const double dp = (double)p;
+            const double up = sqrt(((dp + 1) * (dp + 1) - (double)q * q) * ((dp + 1) * (dp + 1) - (double)qp * qp));
+            const double dn_ = sqrt((dp * dp - (double)q * q) * (dp * dp - (double)qp * qp));
+            dn = ((2 * dp + 1) * (dp * (dp + 1) * cb - qq) * d - (dp + 1) * dn_ * dprev) / (dp * up);
+        }
+        dprev = d;
+        d = dn;
+    }
+}
+
+hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s) {
+    const int L = P.d.L_h, K = 2 * L - 1;
+    dim3 block(128), grid((K * K + 127) / 128, P.n_theta_out);
+    const int64_t rl = dtab_row_len(L);
+    if (P.d.precision == SLSHT_FP64)
+        hipLaunchKernelGGL(wigner_table_kernel<double>, grid, block, 0, s, (double*)P.dtab, L,
+                           P.d.n_phi, P.d.theta_lo, P.n_theta_out, rl);
+    else
+        hipLaunchKernelGGL(wigner_table_kernel<float>, grid, block, 0, s, (float*)P.dtab, L,
+                           P.d.n_phi, P.d.theta_lo, P.n_theta_out, rl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------
+// K2: coupling A^p_q(l,m) = (-1)^m sqrt((2p+1)(2l+1)/(4 pi))
+//        * sum_{l'} sqrt(2l'+1) (l' p l; 0 0 0) (l' p l; m-q q -m) f_{l'}^{m-q}
+// (Gaunt form of the triple product T of Eq:harmonic_formulation).
+//
+// The 3j symbols (j j2 j3; m1 m2 m3), m1 = -m2-m3, are generated over
+// j in [jmin, jmax] by the Schulten-Gordon three-term recursion
+//   j A(j+1) F(j+1) + B(j) F(j) + (j+1) A(j) F(j-1) = 0,
+//   A(j) = sqrt((j^2-(j2-j3)^2)((j2+j3+1)^2-j^2)(j^2-m1^2)),
+//   B(j) = -(2j+1)((j2(j2+1)-j3(j3+1)) m1 - j(j+1)(m3-m2)),
+// run forward from jmin while |F| grows and backward from jmax down to the
+// meeting point (each direction is stable where the true solution grows), then
+// matched, normalised by sum (2j+1) F^2 = 1 and signed so that F(jmax) has the
+// sign (-1)^(j2-j3-m1).  Nothing is stored per j: the caller's sink consumes
+// the unnormalised values and the returned factors finish the job.
+
+struct ThreeJ {
+    int jmin, jmax, jm;
+    double c;       // backward values are multiplied by c to join the forward ones
+    double scale;   // final factor: sign / sqrt(norm)
+};
+
+template <class Sink>
+__device__ ThreeJ threej_two_sided(int j2, int j3, int m2, int m3, Sink& sink) {
+    const int m1 = -m2 - m3;
+    const double dj2 = j2, dj3 = j3, dm1 = m1, dm2 = m2, dm3 = m3;
+    const double dd = dj2 - dj3, ss = (dj2 + dj3 + 1) * (dj2 + dj3 + 1);
+    const double bc = (dj2 * (dj2 + 1) - dj3 * (dj3 + 1)) * dm1, dm = dm3 - dm2;
+    auto Af = [&](double j) {
+        const double t = (j * j - dd * dd) * (ss - j * j) * (j * j - dm1 * dm1);
+        return t > 0.0 ? sqrt(t) : 0.0;
+    };
+    auto Bf = [&](double j) { return -(2 * j + 1) * (bc - j * (j + 1) * dm); };
+
+    ThreeJ r;
+    const int ad = j2 > j3 ? j2 - j3 : j3 - j2;
+    const int am1 = m1 < 0 ? -m1 : m1;
+    r.jmin = ad > am1 ? ad : am1;
+    r.jmax = j2 + j3;
+    int jm = r.jmin;
+    double Fprev = 0.0, Fcur = 1.0;
+    double norm_f = (2.0 * jm + 1.0);
+    sink.fwd(jm, 1.0);
+    if (r.jmax > r.jmin) {
+        double F1;
+        if (r.jmin == 0) F1 = (j2 > 0) ? dm2 / sqrt(dj2 * (dj2 + 1)) : 0.0;   // (1 j j; 0 m -m)/(0 j j; 0 m -m)
+        else F1 = -Bf((double)r.jmin) / ((double)r.jmin * Af((double)r.jmin + 1));
+        if (fabs(F1) > 1.0) {
+            jm = r.jmin + 1;
+            Fprev = 1.0;
+            Fcur = F1;
+            norm_f += (2.0 * jm + 1.0) * F1 * F1;
+            sink.fwd(jm, F1);
+            double Aj = Af((double)jm);
+            while (jm < r.jmax) {
+                const double j = jm;
+                const double Aj1 = Af(j + 1);
+                const double Fn = -(Bf(j) * Fcur + (j + 1) * Aj * Fprev) / (j * Aj1);
+                if (fabs(Fn) <= fabs(Fcur)) break;
+                ++jm;
+                Fprev = Fcur;
+                Fcur = Fn;
+                Aj = Aj1;
+                norm_f += (2.0 * jm + 1.0) * Fn * Fn;
+                sink.fwd(jm, Fn);
+                if (fabs(Fcur) > 1e120) {
+                    Fcur *= 1e-120; Fprev *= 1e-120; norm_f *= 1e-240;
+                    sink.rescale_fwd(1e-120);
+                }
+            }
+        }
+    }
+    r.jm = jm;
+    double norm, top;
+    if (jm < r.jmax) {
+        int j = r.jmax;
+        double Bc = 1.0, Bn = 0.0, topb = 1.0, norm_b = (2.0 * j + 1.0);
+        sink.bwd(j, 1.0);
+        double Aj = Af((double)j), Aj1 = 0.0;
+        for (;;) {
+            const double dj = j;
+            const double Bp = -(Bf(dj) * Bc + dj * Aj1 * Bn) / ((dj + 1) * Aj);
+            --j;
+            Bn = Bc; Bc = Bp; Aj1 = Aj;
+            if (j == jm) break;
+            Aj = Af((double)j);
+            norm_b += (2.0 * j + 1.0) * Bc * Bc;
+            sink.bwd(j, Bc);
+            if (fabs(Bc) > 1e120) {
+                Bc *= 1e-120; Bn *= 1e-120; norm_b *= 1e-240; topb *= 1e-120;
+                sink.rescale_bwd(1e-120);
+            }
+        }
+        r.c = Fcur / Bc;
+        norm = norm_f + r.c * r.c * norm_b;
+        top = r.c * topb;
+    } else {
+        r.c = 1.0;
+        norm = norm_f;
+        top = Fcur;
+    }
+    const double sigma = ((j2 - j3 - m1) & 1) ? -1.0 : 1.0;
+    r.scale = ((top * sigma) > 0.0 ? 1.0 : -1.0) / sqrt(norm);
+    return r;
+}
+
+// Writes the unnormalised sequence into an LDS row; the caller rescales it.
+struct RowSink {
+    double* row;
+    int jmin, jmax, jm_hi, jb_lo;
+    __device__ void fwd(int j, double v) { row[j - jmin] = v; jm_hi = j; }
+    __device__ void bwd(int j, double v) { row[j - jmin] = v; jb_lo = j; }
+    __device__ void rescale_fwd(double s) { for (int j = jmin; j <= jm_hi; ++j) row[j - jmin] *= s; }
+    __device__ void rescale_bwd(double s) { for (int j = jb_lo; j <= jmax; ++j) row[j - jmin] *= s; }
+};
+
+// Accumulates sum_j w_j F(j) with w_j = sqrt(2j+1) Z(j) f_j^{mp} for j < L_f.
+struct DotSink {
+    const double2* f;
+    const double* z;     // Z row for this p: (j p l; 0 0 0) at index j - zlo
+    int zlo, L_f, mp;
+    double fr, fi, br, bi;
+    __device__ void add(int j, double v, double& ar, double& ai) {
+        if (j >= L_f) return;
+        const double w = sqrt(2.0 * j + 1.0) * z[j - zlo] * v;
+        const double2 c = f[(int64_t)j * j + j + mp];
+        ar += w * c.x;
+        ai += w * c.y;
+    }
+    __device__ void fwd(int j, double v) { add(j, v, fr, fi); }
+    __device__ void bwd(int j, double v) { add(j, v, br, bi); }
+    __device__ void rescale_fwd(double s) { fr *= s; fi *= s; }
+    __device__ void rescale_bwd(double s) { br *= s; bi *= s; }
+};
+
+__device__ __forceinline__ void lm_of(int lm_abs, int& l, int& m) {
+    int ll = (int)sqrt((double)lm_abs);
+    while (ll * ll > lm_abs) --ll;
+    while ((ll + 1) * (ll + 1) <= lm_abs) ++ll;
+    l = ll;
+    m = lm_abs - ll * ll - ll;
+}
+
+__global__ void coupling_kernel(const double2* __restrict__ f, double2* __restrict__ A, int L_f,
+                                int L_h, int l_lo) {
+    __shared__ double Z[SLSHT_MAX_LH * SLSHT_MAX_LH];
+    const int lm = blockIdx.x;
+    int l, m;
+    lm_of(lm + l_lo * l_lo, l, m);
+    // Z rows: (j p l; 0 0 0) for j in [|l-p|, l+p], row p at offset p*p.
+    for (int p = threadIdx.x; p < L_h; p += blockDim.x) {
+        RowSink rs;
+        rs.row = Z + p * p;
+        rs.jmin = l > p ? l - p : p - l;
+        rs.jmax = l + p;
+        rs.jm_hi = rs.jmin;
+        rs.jb_lo = rs.jmax;
+        const ThreeJ t = threej_two_sided(p, l, 0, 0, rs);
+        for (int j = t.jmin; j <= t.jmax; ++j)
+            rs.row[j - t.jmin] *= (j <= t.jm ? t.scale : t.c * t.scale);
+    }
+    __syncthreads();
+    const double sm = (m & 1) ? -1.0 : 1.0;
+    const double pref = sm * sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
+    for (int pq = threadIdx.x; pq < L_h * L_h; pq += blockDim.x) {
+        int p, q;
+        lm_of(pq, p, q);
+        DotSink ds;
+        ds.f = f;
+        ds.z = Z + p * p;
+        ds.zlo = l > p ? l - p : p - l;
+        ds.L_f = L_f;
+        ds.mp = m - q;
+        ds.fr = ds.fi = ds.br = ds.bi = 0.0;
+        const ThreeJ t = threej_two_sided(p, l, q, -m, ds);
+        const double k = pref * sqrt(2.0 * p + 1.0) * t.scale;
+        double2 out;
+        out.x = k * (ds.fr + t.c * ds.br);
+        out.y = k * (ds.fi + t.c * ds.bi);
+        A[(int64_t)lm * L_h * L_h + pq] = out;
+    }
+}
+
+hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipStream_t s) {
+    const int n_lm = P.d.l_hi * P.d.l_hi - P.d.l_lo * P.d.l_lo;
+    const int L2 = P.d.L_h * P.d.L_h;
+    const int block = L2 <= 64 ? 64 : (L2 <= 256 ? 256 : 512);
+    hipLaunchKernelGGL(coupling_kernel, dim3(n_lm), dim3(block), 0, s, f, A, P.d.L_f, P.d.L_h,
+                       P.d.l_lo);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------
+// K3: fused synthesis.  One block = one (l, m) item x a tile of tb theta rows.
+//   stage 1 (theta): S_{q,q'}(theta_b) = sum_p A^p_q h_p^{q'} d^p_{q,q'}(theta_b)   -> LDS
+//   stage 2 (omega): U_q(theta_b, omega_c) = sum_{q'} S_{q,q'} e^{-i q' omega_c}, folded
+//                    into P_q = U_q + U_{-q}, M_q = -i (U_q - U_{-q})             -> LDS
+//   stage 3 (phi):   g(phi_a) = U_0 + sum_{q>0} P_q cos(q phi_a) + M_q sin(q phi_a),
+//                    g(phi_{n-a}) = same with the sine part negated                -> HBM
+// The cosine/sine folding uses phi_{n-a} = -phi_a (mod 2 pi), so one lane makes
+// two outputs from 2(L_h-1) real-by-complex products; stage 2 folds omega the
+// same way.  Lane a of stage 3 keeps its cos/sin(q phi_a) in registers for all
+// rows; U_0, P_q, M_q are read as LDS broadcasts.
+
+struct SynthArgs {
+    const double2* A;
+    const double2* h;
+    const void* dtab;
+    const void* twphi;
+    const void* twom;
+    const Item* items;
+    void* g;
+    int64_t dstride;
+    int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp;
+};
+
+template <typename T, int LH>
+__global__ void __launch_bounds__(1024) synth_full_kernel(const SynthArgs a) {
+    using V = typename VecOf<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* S_s = reinterpret_cast<V*>(smem_raw);
+    const int L = a.L, K = a.K;
+    V* X_s = S_s + a.tb * K * K;
+    V* A_s = X_s;
+    V* h_s = X_s + LH * LH;
+    V* PM_s = X_s;                       // [t][c][2][LH], reuses the A/h space
+
+    const int item = blockIdx.x / a.n_tiles;
+    const int tile = blockIdx.x - item * a.n_tiles;
+    const Item it = a.items[item];
+    const int t0 = tile * a.tb;
+    const int tb = min(a.tb, a.n_theta_out - t0);
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    for (int i = tid; i < L * L; i += nth) {
+        A_s[i] = vcast<V>(a.A[(int64_t)it.lm * L * L + i]);
+        h_s[i] = vcast<V>(a.h[i]);
+    }
+    __syncthreads();
+
+    // stage 1: theta contraction
+    const T* dt = reinterpret_cast<const T*>(a.dtab);
+    const int KK = K * K;
+    for (int idx = tid; idx < tb * KK; idx += nth) {
+        const int t = idx / KK;
+        const int r = idx - t * KK;
+        const int qi = r / K;
+        const int q = qi - (L - 1), qp = r - qi * K - (L - 1);
+        const int aq = q < 0 ? -q : q, aqp = qp < 0 ? -qp : qp;
+        const T* drow = dt + (int64_t)(t0 + t) * a.dstride;
+        T sr = 0, si = 0;
+        for (int p = aq > aqp ? aq : aqp; p < L; ++p) {
+            const T dv = drow[dtab_off(p) + (q + p) * (2 * p + 1) + (qp + p)];
+            const V av = A_s[p * p + p + q], hv = h_s[p * p + p + qp];
+            const T pr = av.x * hv.x - av.y * hv.y, pi = av.x * hv.y + av.y * hv.x;
+            sr += pr * dv;
+            si += pi * dv;
+        }
+        S_s[idx] = vmk<V>(sr, si);
+    }
+    __syncthreads();
+
+    // stage 2: omega synthesis, folded into P/M
+    const V* twom = reinterpret_cast<const V*>(a.twom);
+    const int per_t = a.ncp * L;
+    for (int idx = tid; idx < tb * per_t; idx += nth) {
+        const int t = idx / per_t;
+        const int r = idx - t * per_t;
+        const int cs = r / L;
+        const int qa = r - cs * L;
+        const V* Sp = S_s + t * KK + (qa + L - 1) * K;
+        const V* Sm = S_s + t * KK + (L - 1 - qa) * K;
+        V Xp = Sp[L - 1], Xm = Sm[L - 1];
+        V Yp = vmk<V>(0, 0), Ym = vmk<V>(0, 0);
+        for (int k = 1; k < L; ++k) {
+            const V tw = twom[(k - 1) * a.ncp + cs];
+            const V a1 = Sp[L - 1 + k], a2 = Sp[L - 1 - k];
+            const V b1 = Sm[L - 1 + k], b2 = Sm[L - 1 - k];
+            Xp.x += (a1.x + a2.x) * tw.x; Xp.y += (a1.y + a2.y) * tw.x;
+            Yp.x += (a1.x - a2.x) * tw.y; Yp.y += (a1.y - a2.y) * tw.y;
+            Xm.x += (b1.x + b2.x) * tw.x; Xm.y += (b1.y + b2.y) * tw.x;
+            Ym.x += (b1.x - b2.x) * tw.y; Ym.y += (b1.y - b2.y) * tw.y;
+        }
+        Yp = vmul_mi(Yp);
+        Ym = vmul_mi(Ym);
+        const int c1 = cs;
+        int c2 = a.n_omega - cs;
+        if (cs == 0 || c2 == cs) c2 = -1;
+        for (int side = 0; side < 2; ++side) {
+            const int c = side == 0 ? c1 : c2;
+            if (c < 0) break;
+            const V Up = side == 0 ? vadd(Xp, Yp) : vsub(Xp, Yp);
+            V* P = PM_s + ((t * a.n_omega + c) * 2) * LH;
+            V* M = P + LH;
+            if (qa == 0) {
+                P[0] = Up;
+                M[0] = vmk<V>(0, 0);
+                for (int k = L; k < LH; ++k) { P[k] = vmk<V>(0, 0); M[k] = vmk<V>(0, 0); }
+            } else {
+                const V Um = side == 0 ? vadd(Xm, Ym) : vsub(Xm, Ym);
+                P[qa] = vadd(Up, Um);
+                M[qa] = vmul_mi(vsub(Up, Um));
+            }
+        }
+    }
+    __syncthreads();
+
+    // stage 3: phi synthesis and store
+    if (tid < a.nslot) {
+        const int s = tid;
+        const V* twp = reinterpret_cast<const V*>(a.twphi);
+        T cw[LH], sw[LH];
+#pragma unroll
+        for (int k = 1; k < LH; ++k) {
+            if (k < L) {
+                const V tw = twp[(k - 1) * a.nslot + s];
+                cw[k] = tw.x;
+                sw[k] = tw.y;
+            } else {
+                cw[k] = 0;
+                sw[k] = 0;
+            }
+        }
+        V* g = reinterpret_cast<V*>(a.g);
+        const int nrows = a.n_omega * tb;
+        const T msign = (it.m & 1) ? T(-1) : T(1);
+        for (int row = 0; row < nrows; ++row) {
+            const int c = row / tb;
+            const int t = row - c * tb;
+            const V* P = PM_s + ((t * a.n_omega + c) * 2) * LH;
+            const V* M = P + LH;
+            V C = P[0];
+            V Sv = vmk<V>(0, 0);
+#pragma unroll
+            for (int k = 1; k < LH; ++k) {
+                C.x += P[k].x * cw[k];
+                C.y += P[k].y * cw[k];
+                Sv.x += M[k].x * sw[k];
+                Sv.y += M[k].y * sw[k];
+            }
+            const int64_t rowoff = ((int64_t)c * a.n_theta_out + (t0 + t)) * a.n_phi;
+            const int64_t base = (int64_t)it.lm * a.n_omega * a.n_theta_out * a.n_phi + rowoff;
+            const V v1 = vadd(C, Sv), v2 = vsub(C, Sv);
+            g[base + s] = v1;
+            if (s > 0) g[base + a.n_phi - s] = v2;
+            if (it.mirror >= 0) {
+                // g(l,-m) = (-1)^m conj(g(l,m))
+                const int64_t mb = (int64_t)it.mirror * a.n_omega * a.n_theta_out * a.n_phi + rowoff;
+                g[mb + s] = vmk<V>(msign * v1.x, -msign * v1.y);
+                if (s > 0) g[mb + a.n_phi - s] = vmk<V>(msign * v2.x, -msign * v2.y);
+            }
+        }
+    }
+}
+
+static int lh_bucket(int L) { return L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : 32)); }
+
+static size_t synth_lds_bytes(const DevPlan& P, int tb) {
+    const int L = P.d.L_h, K = 2 * L - 1, LH = lh_bucket(L);
+    const size_t v = P.d.precision == SLSHT_FP64 ? 16 : 8;
+    const size_t s = (size_t)tb * K * K;
+    const size_t x = std::max((size_t)2 * LH * LH, (size_t)tb * P.d.n_omega * 2 * LH);
+    return (s + x) * v;
+}
+
+bool choose_synthesis_shape(DevPlan& P, size_t lds_limit) {
+    P.block = ((P.nslot_phi + 63) / 64) * 64;
+    if (P.block > 1024) return false;
+    const size_t soft = 64 * 1024;       // leave room for two blocks per CU
+    int tb = std::min(8, P.n_theta_out);
+    while (tb > 1 && synth_lds_bytes(P, tb) > soft) --tb;
+    if (synth_lds_bytes(P, tb) > lds_limit) return false;
+    P.tb = tb;
+    P.lds_bytes = synth_lds_bytes(P, tb);
+    return true;
+}
+
+template <typename T, int LH>
+static hipError_t launch_synth_t(const DevPlan& P, const SynthArgs& a, hipStream_t s) {
+    const int64_t nblk = (int64_t)P.n_items * a.n_tiles;
+    hipLaunchKernelGGL((synth_full_kernel<T, LH>), dim3((unsigned)nblk), dim3(P.block),
+                       P.lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
+                            hipStream_t s) {
+    SynthArgs a;
+    a.A = A;
+    a.h = h;
+    a.dtab = P.dtab;
+    a.twphi = P.tw_phi;
+    a.twom = P.tw_omega;
+    a.items = P.items;
+    a.g = g;
+    a.dstride = dtab_row_len(P.d.L_h);
+    a.L = P.d.L_h;
+    a.K = 2 * P.d.L_h - 1;
+    a.n_phi = P.d.n_phi;
+    a.n_omega = P.d.n_omega;
+    a.n_theta_out = P.n_theta_out;
+    a.tb = P.tb;
+    a.n_tiles = (P.n_theta_out + P.tb - 1) / P.tb;
+    a.nslot = P.nslot_phi;
+    a.ncp = P.ncp_omega;
+    const bool f64 = P.d.precision == SLSHT_FP64;
+    switch (lh_bucket(P.d.L_h)) {
+        case 4: return f64 ? launch_synth_t<double, 4>(P, a, s) : launch_synth_t<float, 4>(P, a, s);
+        case 8: return f64 ? launch_synth_t<double, 8>(P, a, s) : launch_synth_t<float, 8>(P, a, s);
+        case 16: return f64 ? launch_synth_t<double, 16>(P, a, s) : launch_synth_t<float, 16>(P, a, s);
+        default: return f64 ? launch_synth_t<double, 32>(P, a, s) : launch_synth_t<float, 32>(P, a, s);
+    }
+}
+
+// ------------------------------------------------------------------------------
+// K4: inverse.  f_out[lm] = scale * sum_{c,b,a} q(theta_b) g[lm][c][b][a], one block per lm,
+// FP64 accumulation, wavefront shuffle + LDS reduction.
+
+template <typename V>
+__global__ void __launch_bounds__(256) inverse_kernel(const V* __restrict__ g,
+                                                      const double* __restrict__ qw, int n_phi,
+                                                      int n_theta, int n_omega, double2 scale,
+                                                      double2* __restrict__ f_out) {
+    __shared__ double qs[(SLSHT_MAX_NPHI + 1) / 2];
+    __shared__ double red[2][8];
+    for (int i = threadIdx.x; i < n_theta; i += blockDim.x) qs[i] = qw[i];
+    __syncthreads();
+    const int64_t n = (int64_t)n_omega * n_theta * n_phi;
+    const V* gp = g + (int64_t)blockIdx.x * n;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int b = (int)((i / n_phi) % n_theta);
+        const V v = gp[i];
+        ar += qs[b] * (double)v.x;
+        ai += qs[b] * (double)v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ar += __shfl_xor(ar, o);
+        ai += __shfl_xor(ai, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[0][w] = ar; red[1][w] = ai; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { sr += red[0][k]; si += red[1][k]; }
+        double2 o;
+        o.x = scale.x * sr - scale.y * si;
+        o.y = scale.x * si + scale.y * sr;
+        f_out[blockIdx.x] = o;
+    }
+}
+
+hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,
+                          hipStream_t s) {
+    const int n_lm = P.d.l_hi * P.d.l_hi - P.d.l_lo * P.d.l_lo;
+    if (P.d.precision == SLSHT_FP64)
+        hipLaunchKernelGGL(inverse_kernel<double2>, dim3(n_lm), dim3(256), 0, s,
+                           (const double2*)g, P.qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
+    else
+        hipLaunchKernelGGL(inverse_kernel<float2>, dim3(n_lm), dim3(256), 0, s,
+                           (const float2*)g, P.qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
+    return hipGetLastError();
+}
+
+}  // namespace slsht

@@ -1,0 +1,98 @@
+"""Host-only checks of the C ABI: the library loads, exports every function that
+include/slsht.h declares, and its descriptor checks and footprints behave as
+documented.  No compute call is made (no GPU needed)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1207_5558_amd import _lib as L
+from paper_1207_5558_amd import api
+from paper_1207_5558_amd.inputs import WORKLOADS, workload
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1207_5558_amd import build
+        build.build()
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = L.declared_functions()
+    assert len(names) >= 17
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(L._SIGNATURES), "binding and header disagree"
+
+
+def _desc(**kw):
+    base = dict(L_f=8, L_h=3, l_lo=0, l_hi=8, n_phi=21, n_theta=11, n_omega=5)
+    base.update(kw)
+    return api.make_desc(**base)
+
+
+def test_valid_workloads(lib):
+    for wl in WORKLOADS.values():
+        api.validate(api.desc_for(wl))
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(L_f=0), "L_f"),
+    (dict(L_h=33), "L_h"),
+    (dict(l_lo=5, l_hi=5), "l_lo"),
+    (dict(l_hi=11), "l_hi"),
+    (dict(n_phi=20, n_theta=10), "odd"),
+    (dict(n_theta=10), "n_theta"),
+    (dict(n_omega=0), "n_omega"),
+    (dict(precision="fp64", theta_lo=4, theta_hi=3), "theta"),
+    (dict(theta_hi=12), "theta"),
+])
+def test_invalid_descriptors(lib, kw, msg):
+    d = _desc(**kw)
+    rc = lib.slsht_validate(ctypes.byref(d))
+    assert rc == L.SLSHT_EINVAL
+    assert msg in L.last_error()
+
+
+def test_bad_enums_and_flags(lib):
+    d = _desc()
+    d.precision = 7
+    assert lib.slsht_validate(ctypes.byref(d)) == L.SLSHT_EINVAL
+    d = _desc()
+    d.output_mode = 3
+    assert lib.slsht_validate(ctypes.byref(d)) == L.SLSHT_EINVAL
+    d = _desc()
+    d.flags = 6
+    assert lib.slsht_validate(ctypes.byref(d)) == L.SLSHT_EINVAL
+    assert lib.slsht_validate(None) == L.SLSHT_EINVAL
+
+
+def test_footprints_match_layouts(lib):
+    wl = workload("mid")
+    plan_b, out_b, scr = api.footprint(api.desc_for(wl))
+    assert out_b == wl.samples * 16                  # complex128 FULL
+    wl3 = workload("mid_fp32")
+    assert api.footprint(api.desc_for(wl3))[1] == wl.samples * 8
+    wl5 = workload("large")
+    n_l = wl5.l_hi - wl5.l_lo
+    assert api.footprint(api.desc_for(wl5))[1] == n_l * wl5.n_rho * 4   # float energy
+    # the plan holds the d table (136 rows x 680 entries of FP64) plus small tables
+    assert plan_b >= 136 * 680 * 8
+    assert scr == 0
+    d = _desc(theta_lo=2, theta_hi=5)
+    assert api.footprint(d)[1] == 64 * 5 * 3 * 21 * 16
+
+
+def test_coupling_size(lib):
+    d = api.desc_for(workload("mid"))
+    assert lib.slsht_coupling_size(ctypes.byref(d)) == 1280 * 64
+    assert lib.slsht_coupling_size(None) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        L.lib()

@@ -1,0 +1,153 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Small cases are compared on the whole SO(3) grid; the mid-size workload
+(L_f=128, L_h=8, l in [32,48), 271x136x15 grid) is compared on a seeded sample
+of rotations for every (l, m), in the launch configuration the benchmark
+times.  Bars: relative Frobenius error per degree <= 1e-12 for FP64 and
+<= 1e-5 for FP32-mixed.
+"""
+import numpy as np
+import pytest
+
+from oracle.slsht import oracle_coupling, oracle_g_full, oracle_g_grid
+from paper_1207_5558_amd import api
+from paper_1207_5558_amd.inputs import (draw_coefficients, draw_window, make_inputs,
+                                        rho_subset, workload)
+from tests.gpu_util import (FP32_TOL, FP64_TOL, announce, dev, gather_rho, max_rel, need_gpu,
+                            per_l_rel_err, torch)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.fixture(scope="module")
+def mid_case():
+    wl = workload("mid")
+    f, h = make_inputs(wl)
+    idx = rho_subset(wl, 240, seed=2024)
+    ref = oracle_g_grid(f, h, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta,
+                        wl.n_omega, idx)
+    return wl, f, h, idx, ref
+
+
+def _full_case(L_f, L_h, l_lo, l_hi, n_phi, n_omega, prec, seed, **kw):
+    rng = np.random.default_rng(seed)
+    f = draw_coefficients(rng, L_f, 0.0)
+    h = draw_window(rng, L_h)
+    n_theta = (n_phi + 1) // 2
+    plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, precision=prec,
+                                  **kw))
+    g = plan.forward(dev(f), dev(h)).cpu().numpy()
+    ref = oracle_g_full(f, h, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega)
+    return f, h, g, ref
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_tiny_whole_grid(prec, tol):
+    wl = workload("tiny")
+    announce(f"tiny whole grid {prec}")
+    f, h = make_inputs(wl)
+    plan = api.Plan(api.desc_for(wl, precision=prec))
+    g = plan.forward(dev(f), dev(h)).cpu().numpy()
+    ref = oracle_g_full(f, h, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta, wl.n_omega)
+    errs = per_l_rel_err(g, ref, wl.l_lo, wl.l_hi)
+    assert max(errs.values()) <= tol, errs
+    assert max_rel(g, ref) <= 10 * tol
+
+
+def test_coupling_matches_oracle_tiny_and_mid():
+    for name in ("tiny", "mid"):
+        wl = workload(name)
+        announce(f"coupling {name}")
+        f, _ = make_inputs(wl)
+        plan = api.Plan(api.desc_for(wl))
+        A = plan.coupling(dev(f)).cpu().numpy()
+        ref = oracle_coupling(f, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi)
+        assert max_rel(A, ref) <= FP64_TOL, name
+
+
+def test_coupling_large_degrees():
+    """3j recursions at l' up to 131+31: L_f=132, L_h=32, l in [100,102)."""
+    rng = np.random.default_rng(5)
+    f = draw_coefficients(rng, 132, 2.5, True)
+    announce("coupling large degrees")
+    plan = api.Plan(api.make_desc(132, 32, 100, 102, 327, 164, 63, precision="fp32"))
+    A = plan.coupling(dev(f)).cpu().numpy()
+    ref = oracle_coupling(f, 132, 32, 100, 102)
+    assert max_rel(A, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_mid_sampled_rotations(mid_case, prec, tol):
+    wl, f, h, idx, ref = mid_case
+    announce(f"mid sampled {prec}")
+    plan = api.Plan(api.desc_for(wl, precision=prec))
+    g = plan.forward(dev(f), dev(h))
+    got = gather_rho(g, idx)
+    del g
+    torch.cuda.empty_cache()
+    errs = per_l_rel_err(got, ref, wl.l_lo, wl.l_hi, axis=1)
+    assert max(errs.values()) <= tol, errs
+
+
+def test_mid_real_pair_flag(mid_case):
+    wl, f, h, idx, ref = mid_case
+    announce("mid real-pair")
+    plan = api.Plan(api.desc_for(wl, real_pair=True))
+    g = plan.forward(dev(f), dev(h))
+    got = gather_rho(g, idx)
+    del g
+    torch.cuda.empty_cache()
+    errs = per_l_rel_err(got, ref, wl.l_lo, wl.l_hi, axis=1)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_theta_window_is_a_slice_of_the_full_grid():
+    wl = workload("tiny")
+    f, h = make_inputs(wl)
+    announce("theta window")
+    full = api.Plan(api.desc_for(wl)).forward(dev(f), dev(h))
+    for lo, hi in [(0, 1), (3, 11), (10, 11), (2, 9)]:
+        part = api.Plan(api.desc_for(wl, theta_lo=lo, theta_hi=hi)).forward(dev(f), dev(h))
+        assert torch.equal(part, full[:, :, lo:hi, :])
+
+
+@pytest.mark.parametrize("case", [
+    dict(L_f=6, L_h=1, l_lo=0, l_hi=6, n_phi=13, n_omega=1),          # scalar window
+    dict(L_f=6, L_h=3, l_lo=7, l_hi=8, n_phi=17, n_omega=5),          # top degree only
+    dict(L_f=5, L_h=3, l_lo=0, l_hi=7, n_phi=15, n_omega=4),          # even n_omega
+    dict(L_f=4, L_h=2, l_lo=0, l_hi=5, n_phi=1, n_omega=3),           # one phi, beta=0 only
+    dict(L_f=9, L_h=6, l_lo=2, l_hi=14, n_phi=29, n_omega=11),        # ragged theta tiles
+    dict(L_f=5, L_h=12, l_lo=3, l_hi=6, n_phi=33, n_omega=23),        # L_h > L_f, bucket 16
+])
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_edge_cases_whole_grid(case, prec, tol):
+    announce(f"edge {case} {prec}")
+    f, h, g, ref = _full_case(**case, prec=prec, seed=31)
+    errs = per_l_rel_err(g, ref, case["l_lo"], case["l_hi"])
+    assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_largest_window_band_limit(prec, tol):
+    """L_h = 32 (the largest supported), small signal, theta rows 5..8, sampled rotations."""
+    announce(f"L_h=32 {prec}")
+    rng = np.random.default_rng(3)
+    L_f, L_h, l_lo, l_hi, n_phi, n_omega = 4, 32, 28, 34, 69, 63
+    f = draw_coefficients(rng, L_f, 0.0)
+    h = draw_window(rng, L_h)
+    plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, 35, n_omega, precision=prec,
+                                  theta_lo=5, theta_hi=9))
+    g = plan.forward(dev(f), dev(h))
+    idx = np.stack([rng.integers(0, n_phi, 200), rng.integers(5, 9, 200),
+                    rng.integers(0, n_omega, 200)], 1)
+    ref = oracle_g_grid(f, h, L_f, L_h, l_lo, l_hi, n_phi, 35, n_omega, idx)
+    idx_local = idx.copy()
+    idx_local[:, 1] -= 5
+    got = gather_rho(g, idx_local)
+    errs = per_l_rel_err(got, ref, l_lo, l_hi, axis=1)
+    assert max(errs.values()) <= tol, errs
