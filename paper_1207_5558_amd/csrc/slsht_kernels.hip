@@ -332,8 +332,8 @@ struct SynthArgs {
     int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp;
 };
 
-template <typename T, int LH>
-__global__ void __launch_bounds__(1024) synth_full_kernel(const SynthArgs a) {
+template <typename T, int LH, int NS>
+__global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     using V = typename VecOf<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* S_s = reinterpret_cast<V*>(smem_raw);
@@ -423,55 +423,80 @@ __global__ void __launch_bounds__(1024) synth_full_kernel(const SynthArgs a) {
     }
     __syncthreads();
 
-    // stage 3: phi synthesis and store
-    if (tid < a.nslot) {
-        const int s = tid;
-        const V* twp = reinterpret_cast<const V*>(a.twphi);
-        T cw[LH], sw[LH];
+    // stage 3: phi synthesis and store.  Wave w takes rows w, w + nwaves, ...; a lane
+    // owns NS phi slots of each chunk of 64*NS slots and keeps their cos/sin(q phi_a) in
+    // registers, so every U_0/P_q/M_q broadcast from LDS feeds NS slots (2*NS outputs).
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+    const V* twp = reinterpret_cast<const V*>(a.twphi);
+    V* g = reinterpret_cast<V*>(a.g);
+    const int nrows = a.n_omega * tb;
+    const T msign = (it.m & 1) ? T(-1) : T(1);
+    const int64_t lm_stride = (int64_t)a.n_omega * a.n_theta_out * a.n_phi;
+    for (int cb = 0; cb < a.nslot; cb += 64 * NS) {
+        T cw[NS][LH], sw[NS][LH];
 #pragma unroll
-        for (int k = 1; k < LH; ++k) {
-            if (k < L) {
-                const V tw = twp[(k - 1) * a.nslot + s];
-                cw[k] = tw.x;
-                sw[k] = tw.y;
-            } else {
-                cw[k] = 0;
-                sw[k] = 0;
+        for (int j = 0; j < NS; ++j) {
+            const int s = cb + j * 64 + lane;
+#pragma unroll
+            for (int k = 1; k < LH; ++k) {
+                if (k < L && s < a.nslot) {
+                    const V tw = twp[(k - 1) * a.nslot + s];
+                    cw[j][k] = tw.x;
+                    sw[j][k] = tw.y;
+                } else {
+                    cw[j][k] = 0;
+                    sw[j][k] = 0;
+                }
             }
         }
-        V* g = reinterpret_cast<V*>(a.g);
-        const int nrows = a.n_omega * tb;
-        const T msign = (it.m & 1) ? T(-1) : T(1);
-        for (int row = 0; row < nrows; ++row) {
+        for (int row = wave; row < nrows; row += nwaves) {
             const int c = row / tb;
             const int t = row - c * tb;
             const V* P = PM_s + ((t * a.n_omega + c) * 2) * LH;
             const V* M = P + LH;
-            V C = P[0];
-            V Sv = vmk<V>(0, 0);
+            V C[NS], Sv[NS];
+            const V p0 = P[0];
+#pragma unroll
+            for (int j = 0; j < NS; ++j) { C[j] = p0; Sv[j] = vmk<V>(0, 0); }
 #pragma unroll
             for (int k = 1; k < LH; ++k) {
-                C.x += P[k].x * cw[k];
-                C.y += P[k].y * cw[k];
-                Sv.x += M[k].x * sw[k];
-                Sv.y += M[k].y * sw[k];
+                const V pk = P[k], mk = M[k];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    C[j].x += pk.x * cw[j][k];
+                    C[j].y += pk.y * cw[j][k];
+                    Sv[j].x += mk.x * sw[j][k];
+                    Sv[j].y += mk.y * sw[j][k];
+                }
             }
             const int64_t rowoff = ((int64_t)c * a.n_theta_out + (t0 + t)) * a.n_phi;
-            const int64_t base = (int64_t)it.lm * a.n_omega * a.n_theta_out * a.n_phi + rowoff;
-            const V v1 = vadd(C, Sv), v2 = vsub(C, Sv);
-            g[base + s] = v1;
-            if (s > 0) g[base + a.n_phi - s] = v2;
-            if (it.mirror >= 0) {
-                // g(l,-m) = (-1)^m conj(g(l,m))
-                const int64_t mb = (int64_t)it.mirror * a.n_omega * a.n_theta_out * a.n_phi + rowoff;
-                g[mb + s] = vmk<V>(msign * v1.x, -msign * v1.y);
-                if (s > 0) g[mb + a.n_phi - s] = vmk<V>(msign * v2.x, -msign * v2.y);
+            V* out = g + (int64_t)it.lm * lm_stride + rowoff;
+            V* mout = it.mirror >= 0 ? g + (int64_t)it.mirror * lm_stride + rowoff : nullptr;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                const int s = cb + j * 64 + lane;
+                if (s < a.nslot) {
+                    const V v1 = vadd(C[j], Sv[j]), v2 = vsub(C[j], Sv[j]);
+                    out[s] = v1;
+                    if (s > 0) out[a.n_phi - s] = v2;
+                    if (mout) {
+                        // g(l,-m) = (-1)^m conj(g(l,m))
+                        mout[s] = vmk<V>(msign * v1.x, -msign * v1.y);
+                        if (s > 0) mout[a.n_phi - s] = vmk<V>(msign * v2.x, -msign * v2.y);
+                    }
+                }
             }
         }
     }
 }
 
 static int lh_bucket(int L) { return L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : 32)); }
+
+// Largest number of phi slots per lane whose cos/sin fit the register budget.
+static int ns_max(bool f64, int LH) {
+    if (f64) return LH == 4 ? 4 : (LH == 8 ? 3 : 1);
+    return LH <= 8 ? 4 : (LH == 16 ? 2 : 1);
+}
 
 static size_t synth_lds_bytes(const DevPlan& P, int tb) {
     const int L = P.d.L_h, K = 2 * L - 1, LH = lh_bucket(L);
@@ -482,9 +507,8 @@ static size_t synth_lds_bytes(const DevPlan& P, int tb) {
 }
 
 bool choose_synthesis_shape(DevPlan& P, size_t lds_limit) {
-    P.block = ((P.nslot_phi + 63) / 64) * 64;
-    if (P.block > 1024) return false;
-    const size_t soft = 64 * 1024;       // leave room for two blocks per CU
+    P.block = 256;
+    const size_t soft = 32 * 1024;       // room for several blocks per CU
     int tb = std::min(8, P.n_theta_out);
     while (tb > 1 && synth_lds_bytes(P, tb) > soft) --tb;
     if (synth_lds_bytes(P, tb) > lds_limit) return false;
@@ -493,12 +517,32 @@ bool choose_synthesis_shape(DevPlan& P, size_t lds_limit) {
     return true;
 }
 
-template <typename T, int LH>
-static hipError_t launch_synth_t(const DevPlan& P, const SynthArgs& a, hipStream_t s) {
+template <typename T, int LH, int NS>
+static hipError_t launch_synth_ns(const DevPlan& P, const SynthArgs& a, hipStream_t s) {
     const int64_t nblk = (int64_t)P.n_items * a.n_tiles;
-    hipLaunchKernelGGL((synth_full_kernel<T, LH>), dim3((unsigned)nblk), dim3(P.block),
+    hipLaunchKernelGGL((synth_full_kernel<T, LH, NS>), dim3((unsigned)nblk), dim3(P.block),
                        P.lds_bytes, s, a);
     return hipGetLastError();
+}
+
+template <typename T, int LH>
+static hipError_t launch_synth_t(const DevPlan& P, const SynthArgs& a, hipStream_t s) {
+    const int want = (a.nslot + 63) / 64;
+    const int ns = std::min(want, ns_max(sizeof(T) == 8, LH));
+    if constexpr ((sizeof(T) == 8 && LH >= 16) || (sizeof(T) == 4 && LH == 32)) {
+        return launch_synth_ns<T, LH, 1>(P, a, s);
+    } else if constexpr (sizeof(T) == 4 && LH == 16) {
+        return ns <= 1 ? launch_synth_ns<T, LH, 1>(P, a, s) : launch_synth_ns<T, LH, 2>(P, a, s);
+    } else if constexpr (sizeof(T) == 8 && LH == 8) {
+        return ns <= 1 ? launch_synth_ns<T, LH, 1>(P, a, s)
+             : ns == 2 ? launch_synth_ns<T, LH, 2>(P, a, s)
+                       : launch_synth_ns<T, LH, 3>(P, a, s);
+    } else {
+        return ns <= 1 ? launch_synth_ns<T, LH, 1>(P, a, s)
+             : ns == 2 ? launch_synth_ns<T, LH, 2>(P, a, s)
+             : ns == 3 ? launch_synth_ns<T, LH, 3>(P, a, s)
+                       : launch_synth_ns<T, LH, 4>(P, a, s);
+    }
 }
 
 hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
