@@ -89,17 +89,16 @@ def cpu_baseline(wl, f, h, budget_s: float):
 
     from oracle.slsht import oracle_g_grid
     from paper_1207_5558_amd.inputs import rho_subset
-    n = 32
-    idx = rho_subset(wl, n, seed=99)
-    t = time.perf_counter()
-    oracle_g_grid(f, h, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta, wl.n_omega, idx)
-    dt = time.perf_counter() - t
-    n = int(max(32, min(20000, n * budget_s / max(dt, 1e-3))))
-    idx = rho_subset(wl, n, seed=99)
-    t = time.perf_counter()
-    ref = oracle_g_grid(f, h, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta,
-                        wl.n_omega, idx)
-    dt = time.perf_counter() - t
+    n = 64
+    while True:
+        idx = rho_subset(wl, n, seed=99)
+        t = time.perf_counter()
+        ref = oracle_g_grid(f, h, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta,
+                            wl.n_omega, idx)
+        dt = time.perf_counter() - t
+        if dt >= 0.5 * budget_s or n >= 200000:
+            break
+        n = int(n * min(10.0, budget_s / max(dt, 1e-3)))
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return idx, ref, dt, threads
 
@@ -121,7 +120,19 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 4 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 1 << 29                       # float64 elements: 4 GiB read, 4 GiB written
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the forward transform shards over l-ranges with no exchange step, see "

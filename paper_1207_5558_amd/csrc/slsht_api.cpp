@@ -49,7 +49,7 @@ struct Sizes {
     int64_t n_lm, n_l, n_rho_out;
     size_t vbytes;     // complex output element
     size_t rbytes;     // real (energy) output element
-    size_t dtab, twphi, twom, qw, items, items_l, coupling, out;
+    size_t dtab, twphi, twom, twfull, qw, items, items_l, coupling, out;
 };
 
 bool mul_ok(size_t a, size_t b, size_t& r) {
@@ -84,6 +84,17 @@ int check_desc(const slsht_desc* d) {
     if (d->theta_lo < 0 || thi <= d->theta_lo || thi > d->n_theta)
         return fail(SLSHT_EINVAL, "need 0 <= theta_lo < theta_hi <= n_theta (got %d, %d)",
                     d->theta_lo, d->theta_hi);
+    if (d->output_mode == SLSHT_OUT_ENERGY) {
+        if (d->precision != SLSHT_FP32_MIXED)
+            return fail(SLSHT_EINVAL, "ENERGY output needs precision SLSHT_FP32_MIXED");
+        if (d->n_omega > slsht::kEnergyMaxOmega)
+            return fail(SLSHT_EINVAL, "ENERGY output needs n_omega <= %d", slsht::kEnergyMaxOmega);
+        const int nst = ((d->n_phi + 1) / 2 + 15) / 16, nct = (d->n_omega + 15) / 16;
+        if (nst * nct > slsht::kEnergyMaxTiles)
+            return fail(SLSHT_EINVAL,
+                        "ENERGY output needs ceil(((n_phi+1)/2)/16) * ceil(n_omega/16) <= %d "
+                        "(n_phi <= 1087 at n_omega = 64)", slsht::kEnergyMaxTiles);
+    }
     return SLSHT_OK;
 }
 
@@ -103,6 +114,7 @@ int compute_sizes(const slsht_desc* d, Sizes& s) {
     s.dtab = (size_t)s.n_theta_out * (size_t)slsht::dtab_row_len(L) * s.rbytes;
     s.twphi = (size_t)(L > 1 ? L - 1 : 1) * nslot * s.vbytes;
     s.twom = (size_t)(L > 1 ? L - 1 : 1) * ncp * s.vbytes;
+    s.twfull = d->output_mode == SLSHT_OUT_ENERGY ? (size_t)d->n_phi * sizeof(float2) : 0;
     s.qw = (size_t)d->n_theta * sizeof(double);
     s.items = (size_t)s.n_lm * sizeof(slsht::Item);
     s.items_l = (size_t)s.n_l * sizeof(slsht::Item);
@@ -151,10 +163,10 @@ void twiddles(int L, int n, int nslot, std::vector<T>& out) {
 }
 
 void free_plan_mem(slsht::DevPlan& P) {
-    void* ptrs[] = {P.dtab, P.tw_phi, P.tw_omega, P.qw, P.items, P.items_l, P.A};
+    void* ptrs[] = {P.dtab, P.tw_phi, P.tw_omega, P.tw_full, P.qw, P.items, P.items_l, P.A};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    P.dtab = P.tw_phi = P.tw_omega = nullptr;
+    P.dtab = P.tw_phi = P.tw_omega = P.tw_full = nullptr;
     P.qw = nullptr;
     P.items = P.items_l = nullptr;
     P.A = nullptr;
@@ -181,7 +193,8 @@ int slsht_footprint(const slsht_desc* desc, size_t* plan_bytes, size_t* out_byte
     Sizes s;
     int rc = compute_sizes(desc, s);
     if (rc) return rc;
-    if (plan_bytes) *plan_bytes = s.dtab + s.twphi + s.twom + s.qw + s.items + s.items_l + s.coupling;
+    if (plan_bytes)
+        *plan_bytes = s.dtab + s.twphi + s.twom + s.twfull + s.qw + s.items + s.items_l + s.coupling;
     if (out_bytes) *out_bytes = s.out;
     if (scratch_bytes) *scratch_bytes = 0;
     return SLSHT_OK;
@@ -219,9 +232,15 @@ int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out) {
     if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
         hipSuccess)
         lds_limit = 64 * 1024;
-    if (!slsht::choose_synthesis_shape(P, (size_t)lds_limit)) {
+    if (P.d.output_mode == SLSHT_OUT_FULL && !slsht::choose_synthesis_shape(P, (size_t)lds_limit)) {
         delete pl;
         return fail(SLSHT_EINVAL, "no synthesis tiling fits %d bytes of LDS for this descriptor",
+                    lds_limit);
+    }
+    if (P.d.output_mode == SLSHT_OUT_ENERGY && slsht::energy_lds_for(P) > (size_t)lds_limit) {
+        const size_t need = slsht::energy_lds_for(P);
+        delete pl;
+        return fail(SLSHT_EINVAL, "ENERGY kernel needs %zu bytes of LDS, device allows %d", need,
                     lds_limit);
     }
 
@@ -251,6 +270,7 @@ int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out) {
     alloc((void**)&P.items, s.items);
     alloc((void**)&P.items_l, s.items_l);
     alloc((void**)&P.A, s.coupling);
+    if (s.twfull) alloc(&P.tw_full, s.twfull);
     if (e != hipSuccess) {
         free_plan_mem(P);
         delete pl;
@@ -270,6 +290,16 @@ int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out) {
         e = hipMemcpy(P.tw_phi, tp.data(), tp.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(P.tw_omega, to.data(), to.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && s.twfull) {
+        // cos/sin(2 pi j / n_phi), j < n_phi, for the ENERGY kernel's phi synthesis
+        std::vector<float> tf((size_t)P.d.n_phi * 2);
+        for (int j = 0; j < P.d.n_phi; ++j) {
+            const double ang = 2.0 * M_PI * (double)j / (double)P.d.n_phi;
+            tf[2 * j] = (float)std::cos(ang);
+            tf[2 * j + 1] = (float)std::sin(ang);
+        }
+        e = hipMemcpy(P.tw_full, tf.data(), s.twfull, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemcpy(P.qw, qw.data(), s.qw, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -315,14 +345,15 @@ int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream) {
 int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void* stream) {
     if (!plan || !f || !h || !g) return fail(SLSHT_EINVAL, "NULL argument");
     const slsht::DevPlan& P = plan->P;
-    if (P.d.output_mode != SLSHT_OUT_FULL)
-        return fail(SLSHT_EINVAL, "ENERGY output is not available in this build");
     DeviceGuard guard(plan->device);
     if (!guard.ok) return fail(SLSHT_EDEVICE, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = slsht::launch_coupling(P, (const double2*)f, P.A, s);
     if (e != hipSuccess) return hip_fail(e, "coupling launch");
-    e = slsht::launch_synthesis(P, P.A, (const double2*)h, g, s);
+    if (P.d.output_mode == SLSHT_OUT_FULL)
+        e = slsht::launch_synthesis(P, P.A, (const double2*)h, g, s);
+    else
+        e = slsht::launch_energy(P, P.A, (const double2*)h, (float*)g, s);
     if (e != hipSuccess) return hip_fail(e, "synthesis launch");
     return SLSHT_OK;
 }

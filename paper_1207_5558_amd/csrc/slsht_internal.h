@@ -31,6 +31,7 @@ struct DevPlan {
     void* dtab;          // [n_theta_out][dtab_row_len(L_h)] double or float
     void* tw_phi;        // [L_h-1][nslot_phi] (cos, sin) double2 or float2
     void* tw_omega;      // [L_h-1][ncp_omega] (cos, sin) double2 or float2
+    void* tw_full;       // ENERGY: [n_phi] float2 (cos, sin)(2 pi j / n_phi)
     double* qw;          // [n_theta] beta weights (FULL plans)
     Item* items;         // synthesis work items
     int n_items;
@@ -46,6 +47,12 @@ hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s);
 hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipStream_t s);
 hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
                             hipStream_t s);
+hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
+                         hipStream_t s);
+// ENERGY output limits of the MFMA kernel (checked on the host).
+constexpr int kEnergyMaxOmega = 64;
+constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 waves, 17 each
+size_t energy_lds_for(const DevPlan& P);
 hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,
                           hipStream_t s);
 // Chooses tb / block / lds_bytes for a plan (host only; uses the LDS limit).

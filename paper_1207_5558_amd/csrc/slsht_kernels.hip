@@ -508,7 +508,7 @@ static size_t synth_lds_bytes(const DevPlan& P, int tb) {
 
 bool choose_synthesis_shape(DevPlan& P, size_t lds_limit) {
     P.block = 256;
-    const size_t soft = 32 * 1024;       // room for several blocks per CU
+    const size_t soft = 64 * 1024;       // two blocks per CU (VGPRs allow two waves per SIMD)
     int tb = std::min(8, P.n_theta_out);
     while (tb > 1 && synth_lds_bytes(P, tb) > soft) --tb;
     if (synth_lds_bytes(P, tb) > lds_limit) return false;
@@ -572,6 +572,259 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
         case 16: return f64 ? launch_synth_t<double, 16>(P, a, s) : launch_synth_t<float, 16>(P, a, s);
         default: return f64 ? launch_synth_t<double, 32>(P, a, s) : launch_synth_t<float, 32>(P, a, s);
     }
+}
+
+// ------------------------------------------------------------------------------
+// K3e: energy epilogue, FP32.  One block = one degree l x one theta row; the order m
+// runs inside the block and E(phi_a, theta_b, omega_c; l) = sum_m |g|^2 stays in
+// registers until all orders are done, so g is never written.  Per m:
+//   stage 1 (VALU): S_{q,q'}(theta_b) as in K3                              -> LDS
+//   stage 2 (VALU): omega synthesis folded into P_k, M_k, stored k-major with
+//                   omega contiguous (the B operand layout of the MFMA below)  -> LDS
+//   stage 3 (MFMA): the phi synthesis is a real GEMM per part (Re, Im) and per
+//                   cos/sin half:  C[a][c] = sum_k cos(k phi_a) P_k(c),
+//                   S[a][c] = sum_k sin(k phi_a) M_k(c)   (16x16x4 FP32 MFMA),
+//                   then E(a) += |C+S|^2 and E(n-a) += |C-S|^2 elementwise.
+// A fragments (cos/sin(k phi_a)) come from an n_phi-entry cos/sin table in LDS at
+// index k*a mod n_phi, advanced incrementally.  Lane l of a 16x16x4 FP32 MFMA
+// supplies A[l%16][l/16] and B[l/16][l%16] and receives D rows 4*(l/16)+r, column l%16.
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+struct EnergyArgs {
+    const double2* A;
+    const double2* h;
+    const float* dtab;
+    const float2* twom;
+    const float2* twfull;
+    float* E;
+    int64_t dstride;
+    int L, K, KP, l_lo, n_l, n_phi, n_omega, n_theta_out, nslot, ncp, nst, nct, cstride;
+    int real_pair, nblk;
+};
+
+constexpr int kEnergyWaves = 8;
+
+template <int TPW>
+__global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L = a.L, K = a.K, KK = K * K, KP = a.KP, cs_ = a.cstride;
+    float2* A_s = reinterpret_cast<float2*>(smem_raw);
+    float2* h_s = A_s + L * L;
+    float2* S_s = h_s + L * L;
+    float* PMt = reinterpret_cast<float*>(S_s + KK);          // [4][KP][cstride]
+    float2* tw = reinterpret_cast<float2*>(PMt + 4 * KP * cs_);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    // XCD-aware order: consecutive logical blocks (same theta row, other degrees) land
+    // on one XCD and share its L2 copy of the Wigner-d row.
+    int bid = blockIdx.x;
+    if ((a.nblk & 7) == 0) bid = (blockIdx.x & 7) * (a.nblk >> 3) + (blockIdx.x >> 3);
+    const int t = bid / a.n_l;
+    const int lidx = bid - t * a.n_l;
+    const int l = a.l_lo + lidx;
+
+    for (int i = tid; i < a.n_phi; i += nth) tw[i] = a.twfull[i];
+    for (int i = tid; i < 4 * KP * cs_; i += nth) PMt[i] = 0.0f;
+    for (int i = tid; i < L * L; i += nth) h_s[i] = vcast<float2>(a.h[i]);
+
+    // tile positions of this wave: p = wave + 16 j, slot tile p / nct, omega tile p % nct
+    float Ep[TPW][4], Em[TPW][4];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
+    const int ntp = a.nst * a.nct;
+
+    const float* drow = a.dtab + (int64_t)t * a.dstride;
+    const int nm = a.real_pair ? l + 1 : 2 * l + 1;
+    for (int mi = 0; mi < nm; ++mi) {
+        const int m = a.real_pair ? mi : mi - l;
+        const float wgt = (a.real_pair && m > 0) ? 2.0f : 1.0f;
+        const int64_t lm = (int64_t)l * l + l + m - (int64_t)a.l_lo * a.l_lo;
+        for (int i = tid; i < L * L; i += nth) A_s[i] = vcast<float2>(a.A[lm * L * L + i]);
+        __syncthreads();
+
+        // stage 1: theta contraction
+        for (int idx = tid; idx < KK; idx += nth) {
+            const int qi = idx / K;
+            const int q = qi - (L - 1), qp = idx - qi * K - (L - 1);
+            const int aq = q < 0 ? -q : q, aqp = qp < 0 ? -qp : qp;
+            float sr = 0.0f, si = 0.0f;
+            for (int p = aq > aqp ? aq : aqp; p < L; ++p) {
+                const float dv = drow[dtab_off(p) + (q + p) * (2 * p + 1) + (qp + p)];
+                const float2 av = A_s[p * p + p + q], hv = h_s[p * p + p + qp];
+                sr += (av.x * hv.x - av.y * hv.y) * dv;
+                si += (av.x * hv.y + av.y * hv.x) * dv;
+            }
+            S_s[idx] = vmk<float2>(sr, si);
+        }
+        __syncthreads();
+
+        // stage 2: omega synthesis into P_k, M_k (k = |q|), k-major, omega contiguous
+        for (int idx = tid; idx < a.ncp * L; idx += nth) {
+            const int cs = idx / L;
+            const int qa = idx - cs * L;
+            const float2* Sp = S_s + (qa + L - 1) * K;
+            const float2* Sm = S_s + (L - 1 - qa) * K;
+            float2 Xp = Sp[L - 1], Xm = Sm[L - 1];
+            float2 Yp = vmk<float2>(0, 0), Ym = vmk<float2>(0, 0);
+            for (int k = 1; k < L; ++k) {
+                const float2 tw2 = a.twom[(k - 1) * a.ncp + cs];
+                const float2 a1 = Sp[L - 1 + k], a2 = Sp[L - 1 - k];
+                const float2 b1 = Sm[L - 1 + k], b2 = Sm[L - 1 - k];
+                Xp.x += (a1.x + a2.x) * tw2.x; Xp.y += (a1.y + a2.y) * tw2.x;
+                Yp.x += (a1.x - a2.x) * tw2.y; Yp.y += (a1.y - a2.y) * tw2.y;
+                Xm.x += (b1.x + b2.x) * tw2.x; Xm.y += (b1.y + b2.y) * tw2.x;
+                Ym.x += (b1.x - b2.x) * tw2.y; Ym.y += (b1.y - b2.y) * tw2.y;
+            }
+            Yp = vmul_mi(Yp);
+            Ym = vmul_mi(Ym);
+            int c2 = a.n_omega - cs;
+            if (cs == 0 || c2 == cs) c2 = -1;
+            for (int side = 0; side < 2; ++side) {
+                const int c = side == 0 ? cs : c2;
+                if (c < 0) break;
+                const float2 Up = side == 0 ? vadd(Xp, Yp) : vsub(Xp, Yp);
+                float2 P, M;
+                if (qa == 0) {
+                    P = Up;
+                    M = vmk<float2>(0, 0);
+                } else {
+                    const float2 Um = side == 0 ? vadd(Xm, Ym) : vsub(Xm, Ym);
+                    P = vadd(Up, Um);
+                    M = vmul_mi(vsub(Up, Um));
+                }
+                PMt[(0 * KP + qa) * cs_ + c] = P.x;
+                PMt[(1 * KP + qa) * cs_ + c] = P.y;
+                PMt[(2 * KP + qa) * cs_ + c] = M.x;
+                PMt[(3 * KP + qa) * cs_ + c] = M.y;
+            }
+        }
+        __syncthreads();
+
+        // stage 3: MFMA phi synthesis and energy accumulation.  The lane index is made
+        // opaque here so that the per-tile index arithmetic is redone for every m instead
+        // of being hoisted out of the m loop, where it would pin registers per tile.
+        int lane_o = lane;
+        asm volatile("" : "+v"(lane_o));
+        const int kq = lane_o >> 4, col = lane_o & 15;
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int p = wave + j * kEnergyWaves;
+            if (p >= ntp) break;
+            const int st = p / a.nct, ct = p - st * a.nct;
+            const int as = st * 16 + col;                      // slot of this lane's A rows
+            int step4 = 4 * as;                                // (4 as) mod n_phi, as < n_phi
+            while (step4 >= a.n_phi) step4 -= a.n_phi;
+            int idx = kq * as;                                 // (kq as) mod n_phi, kq < 4
+            while (idx >= a.n_phi) idx -= a.n_phi;
+            f4v cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0}, sre = {0, 0, 0, 0}, sim = {0, 0, 0, 0};
+            const int bcol = ct * 16 + col;
+#pragma unroll 2
+            for (int kk = 0; kk < KP / 4; ++kk) {
+                const float2 cz = tw[idx];
+                const int k = kk * 4 + kq;
+                const float bpr = PMt[(0 * KP + k) * cs_ + bcol];
+                const float bpi = PMt[(1 * KP + k) * cs_ + bcol];
+                const float bmr = PMt[(2 * KP + k) * cs_ + bcol];
+                const float bmi = PMt[(3 * KP + k) * cs_ + bcol];
+                cre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, bpr, cre, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, bpi, cim, 0, 0, 0);
+                sre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, bmr, sre, 0, 0, 0);
+                sim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, bmi, sim, 0, 0, 0);
+                idx += step4;
+                if (idx >= a.n_phi) idx -= a.n_phi;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float pr = cre[r] + sre[r], pi = cim[r] + sim[r];
+                const float mr = cre[r] - sre[r], mi2 = cim[r] - sim[r];
+                Ep[j][r] += wgt * (pr * pr + pi * pi);
+                Em[j][r] += wgt * (mr * mr + mi2 * mi2);
+            }
+            // Materialise this tile's energy here, so that its four MFMA accumulators die
+            // before the next tile starts (otherwise the updates sink to the end of the
+            // unrolled loop and every tile's accumulators stay live at once).
+            asm volatile("" : "+v"(Ep[j][0]), "+v"(Ep[j][1]), "+v"(Ep[j][2]), "+v"(Ep[j][3]),
+                         "+v"(Em[j][0]), "+v"(Em[j][1]), "+v"(Em[j][2]), "+v"(Em[j][3]));
+        }
+        __syncthreads();
+    }
+
+    // store: lane holds slots st*16 + 4*(lane/16) + r of omega column ct*16 + lane%16
+    const int kq = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int p = wave + j * kEnergyWaves;
+        if (p >= ntp) break;
+        const int st = p / a.nct, ct = p - st * a.nct;
+        const int c = ct * 16 + col;
+        if (c >= a.n_omega) continue;
+        float* row = a.E + (((int64_t)lidx * a.n_omega + c) * a.n_theta_out + t) * a.n_phi;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int s = st * 16 + 4 * kq + r;
+            if (s >= a.nslot) continue;
+            row[s] = Ep[j][r];
+            if (s > 0) row[a.n_phi - s] = Em[j][r];
+        }
+    }
+}
+
+static size_t energy_lds_bytes(const DevPlan& P, int KP, int cstride) {
+    const int L = P.d.L_h, K = 2 * L - 1;
+    return (size_t)(2 * L * L + K * K) * sizeof(float2) + (size_t)4 * KP * cstride * sizeof(float) +
+           (size_t)P.d.n_phi * sizeof(float2);
+}
+
+hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
+                         hipStream_t s) {
+    EnergyArgs a;
+    a.A = A;
+    a.h = h;
+    a.dtab = reinterpret_cast<const float*>(P.dtab);
+    a.twom = reinterpret_cast<const float2*>(P.tw_omega);
+    a.twfull = reinterpret_cast<const float2*>(P.tw_full);
+    a.E = E;
+    a.dstride = dtab_row_len(P.d.L_h);
+    a.L = P.d.L_h;
+    a.K = 2 * P.d.L_h - 1;
+    a.KP = (P.d.L_h + 3) / 4 * 4;
+    a.l_lo = P.d.l_lo;
+    a.n_l = P.d.l_hi - P.d.l_lo;
+    a.n_phi = P.d.n_phi;
+    a.n_omega = P.d.n_omega;
+    a.n_theta_out = P.n_theta_out;
+    a.nslot = P.nslot_phi;
+    a.ncp = P.ncp_omega;
+    a.nst = (P.nslot_phi + 15) / 16;
+    a.nct = (P.d.n_omega + 15) / 16;
+    a.cstride = a.nct * 16 + ((a.nct * 16) % 32 == 0 ? 16 : 0);   // rows of k land on other banks
+    a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
+    a.nblk = a.n_l * P.n_theta_out;
+    const size_t lds = energy_lds_bytes(P, a.KP, a.cstride);
+    const int tpw = (a.nst * a.nct + kEnergyWaves - 1) / kEnergyWaves;
+    dim3 grid(a.nblk), block(64 * kEnergyWaves);
+    if (lds > 64 * 1024) {
+        const void* fns[] = {(const void*)energy_kernel<4>, (const void*)energy_kernel<8>,
+                             (const void*)energy_kernel<12>, (const void*)energy_kernel<17>};
+        for (const void* fn : fns)
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    if (tpw <= 4) hipLaunchKernelGGL(energy_kernel<4>, grid, block, lds, s, a);
+    else if (tpw <= 8) hipLaunchKernelGGL(energy_kernel<8>, grid, block, lds, s, a);
+    else if (tpw <= 12) hipLaunchKernelGGL(energy_kernel<12>, grid, block, lds, s, a);
+    else if (tpw <= 17) hipLaunchKernelGGL(energy_kernel<17>, grid, block, lds, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+size_t energy_lds_for(const DevPlan& P) {
+    const int KP = (P.d.L_h + 3) / 4 * 4;
+    const int nct = (P.d.n_omega + 15) / 16;
+    return energy_lds_bytes(P, KP, nct * 16 + ((nct * 16) % 32 == 0 ? 16 : 0));
 }
 
 // ------------------------------------------------------------------------------

@@ -96,3 +96,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="missing"):
         L.lib()
+
+
+def test_energy_descriptor_rules(lib):
+    for kw, msg in [(dict(precision="fp64"), "FP32"), (dict(n_omega=65), "n_omega"),
+                    (dict(n_phi=1089, n_theta=545, n_omega=63), "n_phi")]:
+        d = _desc(output="energy", **{"precision": "fp32", **kw})
+        assert lib.slsht_validate(ctypes.byref(d)) == L.SLSHT_EINVAL
+        assert msg in L.last_error()
+    assert lib.slsht_validate(ctypes.byref(_desc(output="energy", precision="fp32",
+                                                 n_phi=1087, n_theta=544, n_omega=64))) == 0
