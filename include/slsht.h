@@ -189,6 +189,11 @@ int slsht_request_times(slsht_server_t server, uint64_t ticket, double* t_submit
                         double* t_start, double* t_done);
 /* Current server clock (same origin as slsht_request_times). */
 double slsht_server_clock(slsht_server_t server);
+/* Snapshot of the server: bytes of the HBM budget held by admitted requests (inputs,
+ * scratch and unreleased outputs), the budget itself, and the number of queued and
+ * running requests.  Any pointer may be NULL. */
+int slsht_server_stats(slsht_server_t server, size_t* used_bytes, size_t* budget_bytes,
+                       int* n_queued, int* n_running);
 
 #ifdef __cplusplus
 }

@@ -66,6 +66,8 @@ _SIGNATURES = {
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                             ctypes.c_int),
     "slsht_server_clock": ([_P], ctypes.c_double),
+    "slsht_server_stats": ([_P, _SZ, _SZ, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                           ctypes.c_int),
 }
 
 

@@ -1,5 +1,5 @@
 // Host core of the directional SLSHT library: descriptor checks, footprints,
-// plans (device tables), and the forward / coupling / inverse entry points.
+// device tables, plans, and the forward / coupling / inverse entry points.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -16,18 +16,8 @@ namespace {
 
 thread_local std::string g_err;
 
-int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
 int hip_fail(hipError_t e, const char* what) {
-    return fail(SLSHT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return slsht::set_error(SLSHT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
 // Saves and restores the caller's current device around a library call.
@@ -44,86 +34,13 @@ struct DeviceGuard {
     }
 };
 
-struct Sizes {
-    int n_theta_out;
-    int64_t n_lm, n_l, n_rho_out;
-    size_t vbytes;     // complex output element
-    size_t rbytes;     // real (energy) output element
-    size_t dtab, twphi, twom, twfull, qw, items, items_l, coupling, out;
-};
-
 bool mul_ok(size_t a, size_t b, size_t& r) {
     if (a != 0 && b > std::numeric_limits<size_t>::max() / a) return false;
     r = a * b;
     return true;
 }
 
-int check_desc(const slsht_desc* d) {
-    if (!d) return fail(SLSHT_EINVAL, "desc is NULL");
-    if (d->L_f < 1 || d->L_f > SLSHT_MAX_LF)
-        return fail(SLSHT_EINVAL, "L_f=%d outside [1, %d]", d->L_f, SLSHT_MAX_LF);
-    if (d->L_h < 1 || d->L_h > SLSHT_MAX_LH)
-        return fail(SLSHT_EINVAL, "L_h=%d outside [1, %d]", d->L_h, SLSHT_MAX_LH);
-    if (d->l_lo < 0 || d->l_hi <= d->l_lo || d->l_hi > d->L_f + d->L_h - 1)
-        return fail(SLSHT_EINVAL, "need 0 <= l_lo < l_hi <= L_f + L_h - 1 (got l_lo=%d l_hi=%d)",
-                    d->l_lo, d->l_hi);
-    if (d->n_phi < 1 || d->n_phi > SLSHT_MAX_NPHI || (d->n_phi % 2) == 0)
-        return fail(SLSHT_EINVAL, "n_phi=%d must be odd and in [1, %d]", d->n_phi, SLSHT_MAX_NPHI);
-    if (d->n_theta != (d->n_phi + 1) / 2)
-        return fail(SLSHT_EINVAL, "n_theta=%d must equal (n_phi + 1) / 2 = %d", d->n_theta,
-                    (d->n_phi + 1) / 2);
-    if (d->n_omega < 1 || d->n_omega > 4096)
-        return fail(SLSHT_EINVAL, "n_omega=%d outside [1, 4096]", d->n_omega);
-    if (d->precision != SLSHT_FP64 && d->precision != SLSHT_FP32_MIXED)
-        return fail(SLSHT_EINVAL, "unknown precision %d", d->precision);
-    if (d->output_mode != SLSHT_OUT_FULL && d->output_mode != SLSHT_OUT_ENERGY)
-        return fail(SLSHT_EINVAL, "unknown output_mode %d", d->output_mode);
-    if (d->flags & ~(uint32_t)SLSHT_REAL_PAIR)
-        return fail(SLSHT_EINVAL, "unknown flags 0x%x", d->flags);
-    const int thi = d->theta_hi == 0 ? d->n_theta : d->theta_hi;
-    if (d->theta_lo < 0 || thi <= d->theta_lo || thi > d->n_theta)
-        return fail(SLSHT_EINVAL, "need 0 <= theta_lo < theta_hi <= n_theta (got %d, %d)",
-                    d->theta_lo, d->theta_hi);
-    if (d->output_mode == SLSHT_OUT_ENERGY) {
-        if (d->precision != SLSHT_FP32_MIXED)
-            return fail(SLSHT_EINVAL, "ENERGY output needs precision SLSHT_FP32_MIXED");
-        if (d->n_omega > slsht::kEnergyMaxOmega)
-            return fail(SLSHT_EINVAL, "ENERGY output needs n_omega <= %d", slsht::kEnergyMaxOmega);
-        const int nst = ((d->n_phi + 1) / 2 + 15) / 16, nct = (d->n_omega + 15) / 16;
-        if (nst * nct > slsht::kEnergyMaxTiles)
-            return fail(SLSHT_EINVAL,
-                        "ENERGY output needs ceil(((n_phi+1)/2)/16) * ceil(n_omega/16) <= %d "
-                        "(n_phi <= 1087 at n_omega = 64)", slsht::kEnergyMaxTiles);
-    }
-    return SLSHT_OK;
-}
-
-int compute_sizes(const slsht_desc* d, Sizes& s) {
-    int rc = check_desc(d);
-    if (rc) return rc;
-    const int thi = d->theta_hi == 0 ? d->n_theta : d->theta_hi;
-    s.n_theta_out = thi - d->theta_lo;
-    s.n_lm = (int64_t)d->l_hi * d->l_hi - (int64_t)d->l_lo * d->l_lo;
-    s.n_l = d->l_hi - d->l_lo;
-    s.n_rho_out = (int64_t)d->n_phi * s.n_theta_out * d->n_omega;
-    const bool f64 = d->precision == SLSHT_FP64;
-    s.vbytes = f64 ? 16 : 8;
-    s.rbytes = f64 ? 8 : 4;
-    const int L = d->L_h;
-    const size_t nslot = (size_t)(d->n_phi + 1) / 2, ncp = (size_t)d->n_omega / 2 + 1;
-    s.dtab = (size_t)s.n_theta_out * (size_t)slsht::dtab_row_len(L) * s.rbytes;
-    s.twphi = (size_t)(L > 1 ? L - 1 : 1) * nslot * s.vbytes;
-    s.twom = (size_t)(L > 1 ? L - 1 : 1) * ncp * s.vbytes;
-    s.twfull = d->output_mode == SLSHT_OUT_ENERGY ? (size_t)d->n_phi * sizeof(float2) : 0;
-    s.qw = (size_t)d->n_theta * sizeof(double);
-    s.items = (size_t)s.n_lm * sizeof(slsht::Item);
-    s.items_l = (size_t)s.n_l * sizeof(slsht::Item);
-    s.coupling = (size_t)s.n_lm * L * L * sizeof(double2);
-    size_t per = d->output_mode == SLSHT_OUT_FULL ? (size_t)s.n_lm * s.vbytes : (size_t)s.n_l * s.rbytes;
-    if (!mul_ok(per, (size_t)s.n_rho_out, s.out))
-        return fail(SLSHT_EINVAL, "output size overflows size_t");
-    return SLSHT_OK;
-}
+int theta_hi_of(const slsht_desc& d) { return d.theta_hi == 0 ? d.n_theta : d.theta_hi; }
 
 // Beta weights q(beta_b), Section IV-A (definitions of q(beta) and w(m) after
 // eq. Eq:sig_reconstruction_discrete), with L = (n_phi - 1) / 2.  Only even m
@@ -162,17 +79,235 @@ void twiddles(int L, int n, int nslot, std::vector<T>& out) {
         }
 }
 
-void free_plan_mem(slsht::DevPlan& P) {
-    void* ptrs[] = {P.dtab, P.tw_phi, P.tw_omega, P.tw_full, P.qw, P.items, P.items_l, P.A};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
-    P.dtab = P.tw_phi = P.tw_omega = P.tw_full = nullptr;
-    P.qw = nullptr;
-    P.items = P.items_l = nullptr;
-    P.A = nullptr;
+struct TableSizes {
+    size_t dtab, twphi, twom, twfull, qw;
+    size_t total() const { return dtab + twphi + twom + twfull + qw; }
+};
+
+TableSizes table_sizes(const slsht_desc& d) {
+    TableSizes t;
+    const bool f64 = d.precision == SLSHT_FP64;
+    const size_t rb = f64 ? 8 : 4, vb = f64 ? 16 : 8;
+    const int L = d.L_h;
+    const size_t nslot = (size_t)(d.n_phi + 1) / 2, ncp = (size_t)d.n_omega / 2 + 1;
+    const size_t rows = (size_t)(L > 1 ? L - 1 : 1);
+    t.dtab = (size_t)(theta_hi_of(d) - d.theta_lo) * (size_t)slsht::dtab_row_len(L) * rb;
+    t.twphi = rows * nslot * vb;
+    t.twom = rows * ncp * vb;
+    t.twfull = d.output_mode == SLSHT_OUT_ENERGY ? (size_t)d.n_phi * sizeof(float2) : 0;
+    t.qw = (size_t)d.n_theta * sizeof(double);
+    return t;
 }
 
 }  // namespace
+
+namespace slsht {
+
+int set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+Tables::~Tables() {
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != device) (void)hipSetDevice(device);
+    void* ptrs[] = {dtab, tw_phi, tw_omega, tw_full, qw};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+}
+
+int check_desc(const slsht_desc* d) {
+    if (!d) return set_error(SLSHT_EINVAL, "desc is NULL");
+    if (d->L_f < 1 || d->L_f > SLSHT_MAX_LF)
+        return set_error(SLSHT_EINVAL, "L_f=%d outside [1, %d]", d->L_f, SLSHT_MAX_LF);
+    if (d->L_h < 1 || d->L_h > SLSHT_MAX_LH)
+        return set_error(SLSHT_EINVAL, "L_h=%d outside [1, %d]", d->L_h, SLSHT_MAX_LH);
+    if (d->l_lo < 0 || d->l_hi <= d->l_lo || d->l_hi > d->L_f + d->L_h - 1)
+        return set_error(SLSHT_EINVAL,
+                         "need 0 <= l_lo < l_hi <= L_f + L_h - 1 (got l_lo=%d l_hi=%d)", d->l_lo,
+                         d->l_hi);
+    if (d->n_phi < 1 || d->n_phi > SLSHT_MAX_NPHI || (d->n_phi % 2) == 0)
+        return set_error(SLSHT_EINVAL, "n_phi=%d must be odd and in [1, %d]", d->n_phi,
+                         SLSHT_MAX_NPHI);
+    if (d->n_theta != (d->n_phi + 1) / 2)
+        return set_error(SLSHT_EINVAL, "n_theta=%d must equal (n_phi + 1) / 2 = %d", d->n_theta,
+                         (d->n_phi + 1) / 2);
+    if (d->n_omega < 1 || d->n_omega > 4096)
+        return set_error(SLSHT_EINVAL, "n_omega=%d outside [1, 4096]", d->n_omega);
+    if (d->precision != SLSHT_FP64 && d->precision != SLSHT_FP32_MIXED)
+        return set_error(SLSHT_EINVAL, "unknown precision %d", d->precision);
+    if (d->output_mode != SLSHT_OUT_FULL && d->output_mode != SLSHT_OUT_ENERGY)
+        return set_error(SLSHT_EINVAL, "unknown output_mode %d", d->output_mode);
+    if (d->flags & ~(uint32_t)SLSHT_REAL_PAIR)
+        return set_error(SLSHT_EINVAL, "unknown flags 0x%x", d->flags);
+    const int thi = theta_hi_of(*d);
+    if (d->theta_lo < 0 || thi <= d->theta_lo || thi > d->n_theta)
+        return set_error(SLSHT_EINVAL, "need 0 <= theta_lo < theta_hi <= n_theta (got %d, %d)",
+                         d->theta_lo, d->theta_hi);
+    if (d->output_mode == SLSHT_OUT_ENERGY) {
+        if (d->precision != SLSHT_FP32_MIXED)
+            return set_error(SLSHT_EINVAL, "ENERGY output needs precision SLSHT_FP32_MIXED");
+        if (d->n_omega > kEnergyMaxOmega)
+            return set_error(SLSHT_EINVAL, "ENERGY output needs n_omega <= %d", kEnergyMaxOmega);
+        const int nst = ((d->n_phi + 1) / 2 + 15) / 16, nct = (d->n_omega + 15) / 16;
+        if (nst * nct > kEnergyMaxTiles)
+            return set_error(SLSHT_EINVAL,
+                             "ENERGY output needs ceil(((n_phi+1)/2)/16) * ceil(n_omega/16) <= %d "
+                             "(n_phi <= 1087 at n_omega = 64)", kEnergyMaxTiles);
+    }
+    size_t out;
+    const int64_t n_lm = (int64_t)d->l_hi * d->l_hi - (int64_t)d->l_lo * d->l_lo;
+    const int64_t n_l = d->l_hi - d->l_lo;
+    const size_t per = d->output_mode == SLSHT_OUT_FULL
+                           ? (size_t)n_lm * (d->precision == SLSHT_FP64 ? 16 : 8)
+                           : (size_t)n_l * (d->precision == SLSHT_FP64 ? 8 : 4);
+    const size_t n_rho = (size_t)d->n_phi * (thi - d->theta_lo) * d->n_omega;
+    if (!mul_ok(per, n_rho, out)) return set_error(SLSHT_EINVAL, "output size overflows size_t");
+    return SLSHT_OK;
+}
+
+size_t tables_bytes(const slsht_desc& d) { return table_sizes(d).total(); }
+
+size_t coupling_bytes(const slsht_desc& d) {
+    const size_t n_lm = (size_t)d.l_hi * d.l_hi - (size_t)d.l_lo * d.l_lo;
+    return n_lm * d.L_h * d.L_h * sizeof(double2);
+}
+
+size_t output_bytes(const slsht_desc& d) {
+    const size_t n_rho = (size_t)d.n_phi * (theta_hi_of(d) - d.theta_lo) * d.n_omega;
+    if (d.output_mode == SLSHT_OUT_FULL) {
+        const size_t n_lm = (size_t)d.l_hi * d.l_hi - (size_t)d.l_lo * d.l_lo;
+        return n_lm * n_rho * (d.precision == SLSHT_FP64 ? 16 : 8);
+    }
+    return (size_t)(d.l_hi - d.l_lo) * n_rho * (d.precision == SLSHT_FP64 ? 8 : 4);
+}
+
+std::string tables_key(const slsht_desc& d) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d", d.L_h, d.n_phi, d.n_omega, d.theta_lo,
+             theta_hi_of(d), d.precision, d.output_mode);
+    return buf;
+}
+
+size_t device_lds_limit(int device) {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+            hipSuccess || lds <= 0)
+        lds = 64 * 1024;
+    return (size_t)lds;
+}
+
+int make_view(const slsht_desc& d, const std::shared_ptr<Tables>& T, size_t lds_limit,
+              DevPlan& P) {
+    P.d = d;
+    P.d.theta_hi = theta_hi_of(d);
+    P.T = T;
+    P.n_theta_out = P.d.theta_hi - P.d.theta_lo;
+    P.nslot_phi = (P.d.n_phi + 1) / 2;
+    P.ncp_omega = P.d.n_omega / 2 + 1;
+    P.n_lm = (int64_t)P.d.l_hi * P.d.l_hi - (int64_t)P.d.l_lo * P.d.l_lo;
+    if (P.d.flags & SLSHT_REAL_PAIR) {
+        const int64_t a = (int64_t)P.d.l_hi * (P.d.l_hi + 1) / 2;
+        const int64_t b = (int64_t)P.d.l_lo * (P.d.l_lo + 1) / 2;
+        P.n_items = (int)(a - b);
+    } else {
+        P.n_items = (int)P.n_lm;
+    }
+    if (P.d.output_mode == SLSHT_OUT_FULL && !choose_synthesis_shape(P, lds_limit))
+        return set_error(SLSHT_EINVAL, "no synthesis tiling fits %zu bytes of LDS", lds_limit);
+    if (P.d.output_mode == SLSHT_OUT_ENERGY && energy_lds_for(P) > lds_limit)
+        return set_error(SLSHT_EINVAL, "ENERGY kernel needs %zu bytes of LDS, device allows %zu",
+                         energy_lds_for(P), lds_limit);
+    return SLSHT_OK;
+}
+
+int build_tables(const slsht_desc& d, int device, std::shared_ptr<Tables>& out) {
+    const TableSizes ts = table_sizes(d);
+    auto T = std::make_shared<Tables>();
+    T->device = device;
+    T->L_h = d.L_h;
+    T->n_phi = d.n_phi;
+    T->n_theta = d.n_theta;
+    T->n_omega = d.n_omega;
+    T->theta_lo = d.theta_lo;
+    T->theta_hi = theta_hi_of(d);
+    T->precision = d.precision;
+    T->energy = d.output_mode == SLSHT_OUT_ENERGY;
+    T->bytes = ts.total();
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t n) {
+        if (e == hipSuccess && n) e = hipMalloc(p, n);
+    };
+    alloc(&T->dtab, ts.dtab);
+    alloc(&T->tw_phi, ts.twphi);
+    alloc(&T->tw_omega, ts.twom);
+    alloc(&T->tw_full, ts.twfull);
+    alloc((void**)&T->qw, ts.qw);
+    if (e != hipSuccess)
+        return set_error(SLSHT_ENOMEM, "table allocation failed: %s", hipGetErrorString(e));
+
+    const int nslot = (d.n_phi + 1) / 2, ncp = d.n_omega / 2 + 1;
+    if (d.precision == SLSHT_FP64) {
+        std::vector<double> tp, to;
+        twiddles(d.L_h, d.n_phi, nslot, tp);
+        twiddles(d.L_h, d.n_omega, ncp, to);
+        e = hipMemcpy(T->tw_phi, tp.data(), ts.twphi, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(T->tw_omega, to.data(), ts.twom, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> tp, to;
+        twiddles(d.L_h, d.n_phi, nslot, tp);
+        twiddles(d.L_h, d.n_omega, ncp, to);
+        e = hipMemcpy(T->tw_phi, tp.data(), ts.twphi, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(T->tw_omega, to.data(), ts.twom, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && ts.twfull) {
+        // cos/sin(2 pi j / n_phi), j < n_phi, for the ENERGY kernel's phi synthesis
+        std::vector<float> tf((size_t)d.n_phi * 2);
+        for (int j = 0; j < d.n_phi; ++j) {
+            const double ang = 2.0 * M_PI * (double)j / (double)d.n_phi;
+            tf[2 * j] = (float)std::cos(ang);
+            tf[2 * j + 1] = (float)std::sin(ang);
+        }
+        e = hipMemcpy(T->tw_full, tf.data(), ts.twfull, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) {
+        std::vector<double> qw;
+        beta_weights(d.n_phi, d.n_theta, qw);
+        e = hipMemcpy(T->qw, qw.data(), ts.qw, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    // Wigner-d table on the device, on a private stream
+    DevPlan P;
+    P.d = d;
+    P.d.theta_hi = theta_hi_of(d);
+    P.T = T;
+    P.n_theta_out = P.d.theta_hi - P.d.theta_lo;
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = launch_wigner_table(P, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (s) (void)hipStreamDestroy(s);
+    if (e != hipSuccess) return hip_fail(e, "Wigner-d table build");
+    out = T;
+    return SLSHT_OK;
+}
+
+hipError_t enqueue_forward(const DevPlan& P, const double2* f, const double2* h, void* g,
+                           double2* A, hipStream_t s) {
+    hipError_t e = launch_coupling(P, f, A, s);
+    if (e != hipSuccess) return e;
+    if (P.d.output_mode == SLSHT_OUT_FULL) return launch_synthesis(P, A, h, g, s);
+    return launch_energy(P, A, h, (float*)g, s);
+}
+
+}  // namespace slsht
 
 struct slsht_plan_s {
     slsht::DevPlan P;
@@ -183,201 +318,115 @@ extern "C" {
 
 const char* slsht_last_error(void) { return g_err.c_str(); }
 
-int slsht_validate(const slsht_desc* desc) {
-    Sizes s;
-    return compute_sizes(desc, s);
-}
+int slsht_validate(const slsht_desc* desc) { return slsht::check_desc(desc); }
 
 int slsht_footprint(const slsht_desc* desc, size_t* plan_bytes, size_t* out_bytes,
                     size_t* scratch_bytes) {
-    Sizes s;
-    int rc = compute_sizes(desc, s);
+    int rc = slsht::check_desc(desc);
     if (rc) return rc;
-    if (plan_bytes)
-        *plan_bytes = s.dtab + s.twphi + s.twom + s.twfull + s.qw + s.items + s.items_l + s.coupling;
-    if (out_bytes) *out_bytes = s.out;
+    if (plan_bytes) *plan_bytes = slsht::tables_bytes(*desc) + slsht::coupling_bytes(*desc);
+    if (out_bytes) *out_bytes = slsht::output_bytes(*desc);
     if (scratch_bytes) *scratch_bytes = 0;
     return SLSHT_OK;
 }
 
 int64_t slsht_coupling_size(const slsht_desc* desc) {
-    Sizes s;
-    if (compute_sizes(desc, s)) return -1;
-    return s.n_lm * desc->L_h * desc->L_h;
+    if (slsht::check_desc(desc)) return -1;
+    return (int64_t)(slsht::coupling_bytes(*desc) / sizeof(double2));
 }
 
 int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out) {
-    if (!out) return fail(SLSHT_EINVAL, "out is NULL");
+    if (!out) return slsht::set_error(SLSHT_EINVAL, "out is NULL");
     *out = nullptr;
-    Sizes s;
-    int rc = compute_sizes(desc, s);
+    int rc = slsht::check_desc(desc);
     if (rc) return rc;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
-        return fail(SLSHT_EDEVICE, "no HIP device available");
-    if (device < 0 || device >= ndev) return fail(SLSHT_EINVAL, "device %d out of range", device);
+        return slsht::set_error(SLSHT_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev)
+        return slsht::set_error(SLSHT_EINVAL, "device %d out of range", device);
     DeviceGuard guard(device);
-    if (!guard.ok) return fail(SLSHT_EDEVICE, "hipSetDevice(%d) failed", device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice(%d) failed", device);
 
+    std::shared_ptr<slsht::Tables> T;
+    rc = slsht::build_tables(*desc, device, T);
+    if (rc) return rc;
     slsht_plan_s* pl = new slsht_plan_s();
     pl->device = device;
-    slsht::DevPlan& P = pl->P;
-    P.d = *desc;
-    if (P.d.theta_hi == 0) P.d.theta_hi = P.d.n_theta;
-    P.n_theta_out = s.n_theta_out;
-    P.nslot_phi = (P.d.n_phi + 1) / 2;
-    P.ncp_omega = P.d.n_omega / 2 + 1;
-
-    int lds_limit = 0;
-    if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
-        hipSuccess)
-        lds_limit = 64 * 1024;
-    if (P.d.output_mode == SLSHT_OUT_FULL && !slsht::choose_synthesis_shape(P, (size_t)lds_limit)) {
+    rc = slsht::make_view(*desc, T, slsht::device_lds_limit(device), pl->P);
+    if (rc) {
         delete pl;
-        return fail(SLSHT_EINVAL, "no synthesis tiling fits %d bytes of LDS for this descriptor",
-                    lds_limit);
+        return rc;
     }
-    if (P.d.output_mode == SLSHT_OUT_ENERGY && slsht::energy_lds_for(P) > (size_t)lds_limit) {
-        const size_t need = slsht::energy_lds_for(P);
-        delete pl;
-        return fail(SLSHT_EINVAL, "ENERGY kernel needs %zu bytes of LDS, device allows %d", need,
-                    lds_limit);
-    }
-
-    // items: output slot, degree, order, mirrored slot
-    std::vector<slsht::Item> items;
-    const bool pair = (P.d.flags & SLSHT_REAL_PAIR) != 0;
-    for (int l = P.d.l_lo; l < P.d.l_hi; ++l)
-        for (int m = pair ? 0 : -l; m <= l; ++m) {
-            const int base = l * l + l - P.d.l_lo * P.d.l_lo;
-            items.push_back({base + m, l, m, (pair && m > 0) ? base - m : -1});
-        }
-    P.n_items = (int)items.size();
-    std::vector<slsht::Item> items_l;
-    for (int l = P.d.l_lo; l < P.d.l_hi; ++l) items_l.push_back({l - P.d.l_lo, l, 0, -1});
-
-    std::vector<double> qw;
-    beta_weights(P.d.n_phi, P.d.n_theta, qw);
-
-    hipError_t e = hipSuccess;
-    auto alloc = [&](void** p, size_t n) {
-        if (e == hipSuccess) e = hipMalloc(p, n ? n : 16);
-    };
-    alloc(&P.dtab, s.dtab);
-    alloc(&P.tw_phi, s.twphi);
-    alloc(&P.tw_omega, s.twom);
-    alloc((void**)&P.qw, s.qw);
-    alloc((void**)&P.items, s.items);
-    alloc((void**)&P.items_l, s.items_l);
-    alloc((void**)&P.A, s.coupling);
-    if (s.twfull) alloc(&P.tw_full, s.twfull);
+    hipError_t e = hipMalloc((void**)&pl->P.A, slsht::coupling_bytes(*desc));
     if (e != hipSuccess) {
-        free_plan_mem(P);
         delete pl;
-        return fail(SLSHT_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
-    }
-    if (P.d.precision == SLSHT_FP64) {
-        std::vector<double> tp, to;
-        twiddles(P.d.L_h, P.d.n_phi, P.nslot_phi, tp);
-        twiddles(P.d.L_h, P.d.n_omega, P.ncp_omega, to);
-        e = hipMemcpy(P.tw_phi, tp.data(), tp.size() * sizeof(double), hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(P.tw_omega, to.data(), to.size() * sizeof(double), hipMemcpyHostToDevice);
-    } else {
-        std::vector<float> tp, to;
-        twiddles(P.d.L_h, P.d.n_phi, P.nslot_phi, tp);
-        twiddles(P.d.L_h, P.d.n_omega, P.ncp_omega, to);
-        e = hipMemcpy(P.tw_phi, tp.data(), tp.size() * sizeof(float), hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(P.tw_omega, to.data(), to.size() * sizeof(float), hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess && s.twfull) {
-        // cos/sin(2 pi j / n_phi), j < n_phi, for the ENERGY kernel's phi synthesis
-        std::vector<float> tf((size_t)P.d.n_phi * 2);
-        for (int j = 0; j < P.d.n_phi; ++j) {
-            const double ang = 2.0 * M_PI * (double)j / (double)P.d.n_phi;
-            tf[2 * j] = (float)std::cos(ang);
-            tf[2 * j + 1] = (float)std::sin(ang);
-        }
-        e = hipMemcpy(P.tw_full, tf.data(), s.twfull, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess) e = hipMemcpy(P.qw, qw.data(), s.qw, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(P.items, items.data(), items.size() * sizeof(slsht::Item), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(P.items_l, items_l.data(), items_l.size() * sizeof(slsht::Item),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = slsht::launch_wigner_table(P, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-        free_plan_mem(P);
-        delete pl;
-        return hip_fail(e, "plan build");
+        return slsht::set_error(SLSHT_ENOMEM, "coupling scratch: %s", hipGetErrorString(e));
     }
     *out = pl;
     return SLSHT_OK;
 }
 
 int slsht_plan_destroy(slsht_plan_t plan) {
-    if (!plan) return fail(SLSHT_EINVAL, "plan is NULL");
-    DeviceGuard guard(plan->device);
-    (void)hipDeviceSynchronize();
-    free_plan_mem(plan->P);
+    if (!plan) return slsht::set_error(SLSHT_EINVAL, "plan is NULL");
+    {
+        DeviceGuard guard(plan->device);
+        (void)hipDeviceSynchronize();
+        if (plan->P.A) (void)hipFree(plan->P.A);
+    }
     delete plan;
     return SLSHT_OK;
 }
 
 int slsht_plan_desc(slsht_plan_t plan, slsht_desc* out) {
-    if (!plan || !out) return fail(SLSHT_EINVAL, "NULL argument");
+    if (!plan || !out) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
     *out = plan->P.d;
     return SLSHT_OK;
 }
 
 int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream) {
-    if (!plan || !f || !A) return fail(SLSHT_EINVAL, "NULL argument");
+    if (!plan || !f || !A) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
     DeviceGuard guard(plan->device);
-    if (!guard.ok) return fail(SLSHT_EDEVICE, "hipSetDevice failed");
-    hipError_t e = slsht::launch_coupling(plan->P, (const double2*)f, (double2*)A, (hipStream_t)stream);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    hipError_t e = slsht::launch_coupling(plan->P, (const double2*)f, (double2*)A,
+                                          (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "coupling launch");
     return SLSHT_OK;
 }
 
 int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void* stream) {
-    if (!plan || !f || !h || !g) return fail(SLSHT_EINVAL, "NULL argument");
-    const slsht::DevPlan& P = plan->P;
+    if (!plan || !f || !h || !g) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
     DeviceGuard guard(plan->device);
-    if (!guard.ok) return fail(SLSHT_EDEVICE, "hipSetDevice failed");
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = slsht::launch_coupling(P, (const double2*)f, P.A, s);
-    if (e != hipSuccess) return hip_fail(e, "coupling launch");
-    if (P.d.output_mode == SLSHT_OUT_FULL)
-        e = slsht::launch_synthesis(P, P.A, (const double2*)h, g, s);
-    else
-        e = slsht::launch_energy(P, P.A, (const double2*)h, (float*)g, s);
-    if (e != hipSuccess) return hip_fail(e, "synthesis launch");
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    hipError_t e = slsht::enqueue_forward(plan->P, (const double2*)f, (const double2*)h, g,
+                                          plan->P.A, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
     return SLSHT_OK;
 }
 
 int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream) {
-    if (!plan || !g || !h || !f_out) return fail(SLSHT_EINVAL, "NULL argument");
+    if (!plan || !g || !h || !f_out) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
     const slsht::DevPlan& P = plan->P;
     if (P.d.output_mode != SLSHT_OUT_FULL)
-        return fail(SLSHT_EINVAL, "inverse needs a FULL plan");
+        return slsht::set_error(SLSHT_EINVAL, "inverse needs a FULL plan");
     if (P.d.theta_lo != 0 || P.d.theta_hi != P.d.n_theta)
-        return fail(SLSHT_EINVAL, "inverse needs every theta row (theta_lo=0, theta_hi=n_theta)");
+        return slsht::set_error(SLSHT_EINVAL,
+                                "inverse needs every theta row (theta_lo=0, theta_hi=n_theta)");
     if (P.d.n_phi < 2 * P.d.L_h - 1 || P.d.n_omega < 2 * P.d.L_h - 1)
-        return fail(SLSHT_EINVAL, "inverse needs n_phi, n_omega >= 2 L_h - 1");
+        return slsht::set_error(SLSHT_EINVAL, "inverse needs n_phi, n_omega >= 2 L_h - 1");
     DeviceGuard guard(plan->device);
-    if (!guard.ok) return fail(SLSHT_EDEVICE, "hipSetDevice failed");
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
     double2 h00;
     hipError_t e = hipMemcpyAsync(&h00, h, sizeof(double2), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "reading h_0^0");
     const double mag2 = h00.x * h00.x + h00.y * h00.y;
-    if (!(mag2 > 0.0)) return fail(SLSHT_EINVAL, "h_0^0 is zero: the inverse divides by it");
+    if (!(mag2 > 0.0))
+        return slsht::set_error(SLSHT_EINVAL, "h_0^0 is zero: the inverse divides by it");
     // scale = 1 / (n_phi^2 n_omega sqrt(16 pi^3) h00)
-    const double k = 1.0 / ((double)P.d.n_phi * P.d.n_phi * P.d.n_omega * std::sqrt(16.0 * M_PI * M_PI * M_PI));
+    const double k = 1.0 / ((double)P.d.n_phi * P.d.n_phi * P.d.n_omega *
+                            std::sqrt(16.0 * M_PI * M_PI * M_PI));
     double2 scale;
     scale.x = k * h00.x / mag2;
     scale.y = -k * h00.y / mag2;

@@ -3,8 +3,11 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
 #include <cstddef>
 #include <cstdint>
+#include <memory>
+#include <string>
 
 #include "../../include/slsht.h"
 
@@ -16,31 +19,58 @@ inline int64_t dtab_row_len(int L) { return (int64_t)L * (4LL * L * L - 1) / 3; 
 // Offset of degree p inside one theta row of the table.
 __host__ __device__ inline int dtab_off(int p) { return p * (4 * p * p - 1) / 3; }
 
-// Work item of the synthesis kernels: output slot lm, degree l, order m, and
-// the slot of order -m that is filled by conjugate symmetry (-1 if none).
-struct Item {
-    int lm, l, m, mirror;
+// Device tables shared by every descriptor with the same window band-limit, grid,
+// theta rows, precision and output kind: Wigner-d(theta_b), phi/omega twiddles,
+// beta weights.  Freed when the last plan using them goes away.
+struct Tables {
+    int device = 0;
+    int L_h = 0, n_phi = 0, n_theta = 0, n_omega = 0, theta_lo = 0, theta_hi = 0, precision = 0;
+    bool energy = false;
+    void* dtab = nullptr;       // [n_theta_out][dtab_row_len(L_h)] double or float
+    void* tw_phi = nullptr;     // [L_h-1][(n_phi+1)/2] (cos, sin) double2 or float2
+    void* tw_omega = nullptr;   // [L_h-1][n_omega/2+1] (cos, sin) double2 or float2
+    void* tw_full = nullptr;    // ENERGY: [n_phi] float2 (cos, sin)(2 pi j / n_phi)
+    double* qw = nullptr;       // [n_theta] beta weights of the inverse
+    size_t bytes = 0;
+    ~Tables();
 };
 
-// Device-resident plan data, shared by the launchers.
+// Everything a launch needs for one descriptor.
 struct DevPlan {
-    slsht_desc d;
-    int n_theta_out;     // theta_hi - theta_lo
-    int nslot_phi;       // (n_phi + 1) / 2 phi "slots": a and n_phi - a share one
-    int ncp_omega;       // n_omega / 2 + 1 omega slots
-    void* dtab;          // [n_theta_out][dtab_row_len(L_h)] double or float
-    void* tw_phi;        // [L_h-1][nslot_phi] (cos, sin) double2 or float2
-    void* tw_omega;      // [L_h-1][ncp_omega] (cos, sin) double2 or float2
-    void* tw_full;       // ENERGY: [n_phi] float2 (cos, sin)(2 pi j / n_phi)
-    double* qw;          // [n_theta] beta weights (FULL plans)
-    Item* items;         // synthesis work items
-    int n_items;
-    Item* items_l;       // ENERGY: one item per degree (lm = l - l_lo)
-    double2* A;          // coupling scratch [n_lm][L_h^2]
-    int tb;              // theta rows per synthesis block
-    int block;           // threads per synthesis block
-    size_t lds_bytes;    // dynamic LDS of the synthesis kernel
+    slsht_desc d{};                 // theta_hi resolved
+    std::shared_ptr<Tables> T;
+    int n_theta_out = 0;            // theta_hi - theta_lo
+    int nslot_phi = 0;              // (n_phi + 1) / 2 phi slots: a and n_phi - a share one
+    int ncp_omega = 0;              // n_omega / 2 + 1 omega slots
+    int64_t n_lm = 0;
+    int n_items = 0;                // synthesis items: n_lm, or the m >= 0 pairs with REAL_PAIR
+    double2* A = nullptr;           // coupling scratch owned by a public plan
+    int tb = 1;                     // theta rows per synthesis block
+    int block = 256;                // threads per synthesis block
+    size_t lds_bytes = 0;           // dynamic LDS of the synthesis kernel
 };
+
+// Thread-local error message (slsht_last_error), shared by the host files.
+int set_error(int code, const char* fmt, ...);
+
+// Host-only checks and sizes.
+int check_desc(const slsht_desc* d);
+size_t tables_bytes(const slsht_desc& d);
+size_t coupling_bytes(const slsht_desc& d);
+size_t output_bytes(const slsht_desc& d);
+// Tables are keyed by the fields they depend on.
+std::string tables_key(const slsht_desc& d);
+// Builds the device tables for d on `device` (which must be current); synchronises
+// only its own stream.  Returns SLSHT_OK or an error status (message set).
+int build_tables(const slsht_desc& d, int device, std::shared_ptr<Tables>& out);
+// Fills a DevPlan for d over existing tables (host only, no allocation).
+int make_view(const slsht_desc& d, const std::shared_ptr<Tables>& T, size_t lds_limit,
+              DevPlan& P);
+// Enqueues coupling + synthesis (FULL or ENERGY) of one forward transform on s,
+// with A as the coupling scratch (coupling_bytes(d)).
+hipError_t enqueue_forward(const DevPlan& P, const double2* f, const double2* h, void* g,
+                           double2* A, hipStream_t s);
+size_t device_lds_limit(int device);
 
 // Launchers; each returns hipSuccess or the launch error.
 hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s);
@@ -49,13 +79,14 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
                             hipStream_t s);
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
                          hipStream_t s);
+hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,
+                          hipStream_t s);
+// Chooses tb / block / lds_bytes of the FULL synthesis (host only).
+bool choose_synthesis_shape(DevPlan& P, size_t lds_limit);
+size_t energy_lds_for(const DevPlan& P);
+
 // ENERGY output limits of the MFMA kernel (checked on the host).
 constexpr int kEnergyMaxOmega = 64;
 constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 waves, 17 each
-size_t energy_lds_for(const DevPlan& P);
-hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,
-                          hipStream_t s);
-// Chooses tb / block / lds_bytes for a plan (host only; uses the LDS limit).
-bool choose_synthesis_shape(DevPlan& P, size_t lds_limit);
 
 }  // namespace slsht

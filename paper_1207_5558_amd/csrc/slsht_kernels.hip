@@ -108,10 +108,10 @@ hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s) {
     dim3 block(128), grid((K * K + 127) / 128, P.n_theta_out);
     const int64_t rl = dtab_row_len(L);
     if (P.d.precision == SLSHT_FP64)
-        hipLaunchKernelGGL(wigner_table_kernel<double>, grid, block, 0, s, (double*)P.dtab, L,
+        hipLaunchKernelGGL(wigner_table_kernel<double>, grid, block, 0, s, (double*)P.T->dtab, L,
                            P.d.n_phi, P.d.theta_lo, P.n_theta_out, rl);
     else
-        hipLaunchKernelGGL(wigner_table_kernel<float>, grid, block, 0, s, (float*)P.dtab, L,
+        hipLaunchKernelGGL(wigner_table_kernel<float>, grid, block, 0, s, (float*)P.T->dtab, L,
                            P.d.n_phi, P.d.theta_lo, P.n_theta_out, rl);
     return hipGetLastError();
 }
@@ -326,11 +326,36 @@ struct SynthArgs {
     const void* dtab;
     const void* twphi;
     const void* twom;
-    const Item* items;
     void* g;
     int64_t dstride;
-    int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp;
+    int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp, l_lo, real_pair;
 };
+
+// Synthesis item -> output slot lm, degree l, order m and the slot of order -m that is
+// filled by conjugate symmetry (-1 if none).  Without REAL_PAIR the items are the lm
+// slots themselves; with it they enumerate (l, m), l_lo <= l, 0 <= m <= l, in order.
+struct Item {
+    int lm, l, m, mirror;
+};
+
+__device__ __forceinline__ Item item_decode(int item, int l_lo, int real_pair) {
+    Item it;
+    if (!real_pair) {
+        lm_of(item + l_lo * l_lo, it.l, it.m);
+        it.lm = item;
+        it.mirror = -1;
+        return it;
+    }
+    const int64_t x = item + (int64_t)l_lo * (l_lo + 1) / 2;   // = l(l+1)/2 + m
+    int l = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(l + 1) * (l + 2) / 2 <= x) ++l;
+    while ((int64_t)l * (l + 1) / 2 > x) --l;
+    it.l = l;
+    it.m = (int)(x - (int64_t)l * (l + 1) / 2);
+    it.lm = l * l + l + it.m - l_lo * l_lo;
+    it.mirror = it.m > 0 ? l * l + l - it.m - l_lo * l_lo : -1;
+    return it;
+}
 
 template <typename T, int LH, int NS>
 __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
@@ -345,7 +370,7 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
 
     const int item = blockIdx.x / a.n_tiles;
     const int tile = blockIdx.x - item * a.n_tiles;
-    const Item it = a.items[item];
+    const Item it = item_decode(item, a.l_lo, a.real_pair);
     const int t0 = tile * a.tb;
     const int tb = min(a.tb, a.n_theta_out - t0);
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -550,10 +575,9 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
     SynthArgs a;
     a.A = A;
     a.h = h;
-    a.dtab = P.dtab;
-    a.twphi = P.tw_phi;
-    a.twom = P.tw_omega;
-    a.items = P.items;
+    a.dtab = P.T->dtab;
+    a.twphi = P.T->tw_phi;
+    a.twom = P.T->tw_omega;
     a.g = g;
     a.dstride = dtab_row_len(P.d.L_h);
     a.L = P.d.L_h;
@@ -565,6 +589,8 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
     a.n_tiles = (P.n_theta_out + P.tb - 1) / P.tb;
     a.nslot = P.nslot_phi;
     a.ncp = P.ncp_omega;
+    a.l_lo = P.d.l_lo;
+    a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     const bool f64 = P.d.precision == SLSHT_FP64;
     switch (lh_bucket(P.d.L_h)) {
         case 4: return f64 ? launch_synth_t<double, 4>(P, a, s) : launch_synth_t<float, 4>(P, a, s);
@@ -784,9 +810,9 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
     EnergyArgs a;
     a.A = A;
     a.h = h;
-    a.dtab = reinterpret_cast<const float*>(P.dtab);
-    a.twom = reinterpret_cast<const float2*>(P.tw_omega);
-    a.twfull = reinterpret_cast<const float2*>(P.tw_full);
+    a.dtab = reinterpret_cast<const float*>(P.T->dtab);
+    a.twom = reinterpret_cast<const float2*>(P.T->tw_omega);
+    a.twfull = reinterpret_cast<const float2*>(P.T->tw_full);
     a.E = E;
     a.dstride = dtab_row_len(P.d.L_h);
     a.L = P.d.L_h;
@@ -871,10 +897,10 @@ hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double
     const int n_lm = P.d.l_hi * P.d.l_hi - P.d.l_lo * P.d.l_lo;
     if (P.d.precision == SLSHT_FP64)
         hipLaunchKernelGGL(inverse_kernel<double2>, dim3(n_lm), dim3(256), 0, s,
-                           (const double2*)g, P.qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
+                           (const double2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
     else
         hipLaunchKernelGGL(inverse_kernel<float2>, dim3(n_lm), dim3(256), 0, s,
-                           (const float2*)g, P.qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
+                           (const float2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
     return hipGetLastError();
 }
 

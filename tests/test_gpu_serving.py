@@ -1,0 +1,122 @@
+"""Serving loop on the GPU: continuous batching through slsht_submit / slsht_poll.
+
+A mix of uneven requests (band-limits, l-windows, precisions, output kinds) is
+submitted at once into a budget that forces queueing; every result must equal,
+bit for bit, the same transform run alone through a plan, the server must never
+hold more than its budget, and the error paths must report the documented
+statuses.
+"""
+import numpy as np
+import pytest
+
+from oracle.slsht import oracle_g_grid
+from paper_1207_5558_amd import _lib as L
+from paper_1207_5558_amd import api
+from paper_1207_5558_amd.inputs import (ServingRequest, draw_coefficients, draw_window,
+                                        grid_dims, serving_stream)
+from paper_1207_5558_amd.serving import Server, request_desc, run_stream
+from tests.gpu_util import FP32_TOL, FP64_TOL, announce, dev, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _mix(n, seed=3):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        L_f = int(rng.choice([12, 20, 33]))
+        L_h = int(rng.choice([3, 4, 8, 16]))
+        l_lo = int(rng.integers(0, L_f - 4))
+        reqs.append(ServingRequest(0.0, L_f, L_h, l_lo, l_lo + 5,
+                                   "fp64" if i % 2 else "fp32", 1000 + i))
+    return reqs
+
+
+def _alone(req, f, h, output="full"):
+    n_phi, n_theta, n_omega = req.grid
+    plan = api.Plan(api.make_desc(req.L_f, req.L_h, req.l_lo, req.l_hi, n_phi, n_theta, n_omega,
+                                  precision=req.precision, output=output))
+    return plan.forward(dev(f), dev(h)).cpu().numpy().ravel()
+
+
+def test_mix_equals_alone_bitwise():
+    announce("serving mix vs alone")
+    reqs = _mix(24)
+    inputs = [r.inputs() for r in reqs]
+    biggest = max(api.footprint(request_desc(r))[1] for r in reqs)
+    srv = Server(hbm_budget=3 * biggest + (64 << 20), n_streams=4)
+    tickets = [srv.submit(request_desc(r), f, h) for r, (f, h) in zip(reqs, inputs)]
+    u, b, q, running = srv.stats()
+    assert u <= b
+    results = {}
+    for i, t in enumerate(tickets):
+        srv.wait(t, 120000)
+        st, ptr, n, err = srv.poll(t)
+        assert st == L.REQ_DONE, (i, st, err)
+        results[i] = srv.result(t, np.complex128 if reqs[i].precision == "fp64" else np.complex64)
+        srv.release(t)
+        u, b, _, _ = srv.stats()
+        assert u <= b
+    srv.close()
+    for i, r in enumerate(reqs):
+        alone = _alone(r, *inputs[i])
+        assert np.array_equal(results[i], alone), i
+
+
+def test_stream_respects_budget_and_matches_oracle():
+    """A short Poisson stream shaped like the serving workload (width-8 windows,
+    L_h in {4,8,16}, half FP64 / half FP32), scaled down in L_f; two results are
+    checked against the oracle on sampled rotations."""
+    announce("serving stream")
+    reqs = serving_stream(30, rate_hz=400.0, seed=11, L_f_choices=(16, 24, 32))
+    srv = Server(hbm_budget=2 << 30, n_streams=4)
+    res = run_stream(srv, reqs, keep=lambda i: i in (0, 1))
+    budget = srv.stats()[1]
+    srv.close()
+    assert np.all(np.isfinite(res["latency_s"])) and np.all(res["latency_s"] > 0)
+    assert res["peak_used_bytes"] <= budget
+    for i in (0, 1):
+        r = reqs[i]
+        f, h = r.inputs()
+        n_phi, n_theta, n_omega = r.grid
+        rng = np.random.default_rng(i)
+        idx = np.stack([rng.integers(0, n_phi, 40), rng.integers(0, n_theta, 40),
+                        rng.integers(0, n_omega, 40)], 1)
+        ref = oracle_g_grid(f, h, r.L_f, r.L_h, r.l_lo, r.l_hi, n_phi, n_theta, n_omega, idx)
+        g = res["kept"][i].reshape(-1, n_omega, n_theta, n_phi)
+        got = g[:, idx[:, 2], idx[:, 1], idx[:, 0]].T
+        tol = FP64_TOL if r.precision == "fp64" else FP32_TOL
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= tol
+
+
+def test_energy_requests_and_error_paths():
+    announce("serving energy + errors")
+    rng = np.random.default_rng(9)
+    f = draw_coefficients(rng, 20)
+    h = draw_window(rng, 8)
+    n_phi, n_theta, n_omega = grid_dims(20, 8)
+    d_e = api.make_desc(20, 8, 4, 12, n_phi, n_theta, n_omega, precision="fp32", output="energy")
+    srv = Server(hbm_budget=256 << 20, n_streams=2)
+    t = srv.submit(d_e, f, h)
+    srv.wait(t)
+    got = srv.result(t, np.float32)
+    plan = api.Plan(d_e)
+    assert np.array_equal(got, plan.forward(dev(f), dev(h)).cpu().numpy().ravel())
+    srv.release(t)
+    with pytest.raises(L.SlshtError) as e:
+        srv.release(t)
+    assert e.value.status == L.SLSHT_ENOTFOUND
+    big = api.make_desc(192, 16, 176, 184, *grid_dims(192, 16))
+    with pytest.raises(L.SlshtError) as e:
+        srv.submit(big, np.zeros(192 * 192, complex), np.zeros(256, complex))
+    assert e.value.status == L.SLSHT_ETOOBIG
+    bad = api.make_desc(20, 8, 4, 40, n_phi, n_theta, n_omega)
+    with pytest.raises(L.SlshtError) as e:
+        srv.submit(bad, f, h)
+    assert e.value.status == L.SLSHT_EINVAL
+    srv.close()
