@@ -103,6 +103,81 @@ def cpu_baseline(wl, f, h, budget_s: float):
     return idx, ref, dt, threads
 
 
+def energy_flops_per_m_theta(wl) -> float:
+    """Algorithmic flops of one (m, theta) pair of the ENERGY kernel: the folded phi
+    GEMMs (cos part K = L_h, sin part K = L_h - 1, real and imaginary parts), the theta
+    contraction over sum_p (2p+1)^2 terms, the folded omega synthesis and |g|^2."""
+    L, nslot, no = wl.L_h, (wl.n_phi + 1) // 2, wl.n_omega
+    phi = 2 * nslot * no * 2 * (L + (L - 1))
+    theta = 10 * L * (4 * L * L - 1) // 3
+    omega = (no // 2 + 1) * L * (L - 1) * 16
+    energy = 4 * no * wl.n_phi
+    return float(phi + theta + omega + energy)
+
+
+def energy_leg(torch, api, steps):
+    """Topography-like workload (L_f=512, L_h=32, l in [100,116), 1087x544x63, FP32-mixed),
+    output reduced to sum_m |g|^2; timed for all orders and for the real-pair path."""
+    from paper_1207_5558_amd.inputs import make_inputs, workload
+    wl = workload("large")
+    f, h = make_inputs(wl)
+    ft, ht = torch.from_numpy(f).to("cuda:0"), torch.from_numpy(h).to("cuda:0")
+    out = {"workload": "large: L_f=512, L_h=32, l in [100,116) all m (3456 (l,m)), "
+                       "1087 x 544 x 63 grid, FP32-mixed, energy output",
+           "samples_per_step": wl.samples}
+    fl = energy_flops_per_m_theta(wl)
+    for name, pair in (("all_orders", False), ("real_pair", True)):
+        plan = api.Plan(api.desc_for(wl, real_pair=pair), device=0)
+        E = plan.empty_output()
+        plan.forward(ft, ht, E)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        stream = torch.cuda.current_stream()
+        for s_, e_ in ev:
+            s_.record(stream)
+            plan.forward(ft, ht, E, stream=stream)
+            e_.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([s_.elapsed_time(e_) for s_, e_ in ev]))
+        n_m_theta = (wl.n_lm if not pair else sum(l + 1 for l in range(wl.l_lo, wl.l_hi))) \
+            * wl.n_theta
+        tf = fl * n_m_theta / (ms * 1e-3) / 1e12
+        out[name] = {"ms_per_step": ms, "value": wl.samples / (ms * 1e-3), "unit": "samples/s",
+                     "roofline": {"bound": "mfma", "achieved": tf, "peak": 157.3,
+                                  "unit": "TFLOP/s", "frac": tf / 157.3,
+                                  "algorithmic_flops_per_launch": fl * n_m_theta}}
+        log(f"energy {name}: {ms:.1f} ms, {wl.samples / (ms * 1e-3):.3e} samples/s, "
+            f"{tf:.1f} TFLOP/s")
+        del E, plan
+        torch.cuda.empty_cache()
+    return out
+
+
+def serving_leg(n, rate):
+    """Continuous batching of the serving workload: n requests with Poisson arrivals at
+    `rate` req/s, L_f in {32..192}, L_h in {4,8,16}, width-8 l-windows, half FP64 and half
+    FP32-mixed; latency is arrival -> done on the server clock."""
+    import torch
+    from paper_1207_5558_amd.inputs import serving_stream
+    from paper_1207_5558_amd.serving import Server, run_stream
+    torch.cuda.empty_cache()
+    reqs = serving_stream(n, rate_hz=rate, seed=7)
+    inputs = [r.inputs() for r in reqs]
+    tot = sum(r.samples for r in reqs)
+    srv = Server(hbm_budget=200 << 30, n_streams=4)
+    res = run_stream(srv, reqs, inputs=inputs)
+    srv.close()
+    lat = res["latency_s"] * 1e3
+    out = {"requests": n, "arrival_rate_hz": rate, "hbm_budget_bytes": 200 << 30,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "value": tot / res["span_s"], "unit": "samples/s",
+           "span_s": res["span_s"], "samples": tot, "peak_budget_used_bytes": res["peak_used_bytes"]}
+    log(f"serving: {n} req at {rate}/s: p50 {out['p50_ms']:.2f} ms, p99 {out['p99_ms']:.2f} ms, "
+        f"{out['value']:.3e} samples/s")
+    return out
+
+
 def rel_err_per_l(got, ref, l_lo, l_hi):
     out = []
     for l in range(l_lo, l_hi):
@@ -120,6 +195,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--no-energy", action="store_true", help="skip the ENERGY workload leg")
+    ap.add_argument("--steps-energy", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-n", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, req/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -135,8 +215,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the forward transform shards over l-ranges with no exchange step, see "
-              "DESIGN.md, but only the one-GPU kernel is built and measured)", file=sys.stderr)
+              "(the forward transform shards over l-ranges with no exchange step, but only "
+              "the one-GPU kernel is built and measured)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -213,6 +293,13 @@ def main():
                           "roofline": {"bound": "hbm", "achieved": alg32 / (k32 * 1e-3) / 1e9,
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": alg32 / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+    # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
+    # fit beside them in 288 GB of HBM
+    if not args.no_energy:
+        line["energy_large"] = energy_leg(torch, api, args.steps_energy)
+    if not args.no_serve:
+        line["serving"] = serving_leg(args.serve_n, args.serve_rate)
 
     if not args.no_cpu:
         log("CPU baseline: oracle on a sample of rotations")

@@ -33,8 +33,9 @@
  *  - Output index of (l, m): lm = l*l + l + m - l_lo*l_lo.
  *    FULL output:   g[lm][c][b - theta_lo][a]  (phi contiguous), complex128
  *                   (SLSHT_FP64) or complex64 (SLSHT_FP32_MIXED).
- *    ENERGY output: E[l - l_lo][c][b - theta_lo][a] = sum_{|m|<=l} |g|^2,
- *                   double (SLSHT_FP64) or float (SLSHT_FP32_MIXED).
+ *    ENERGY output: E[l - l_lo][c][b - theta_lo][a] = sum_{|m|<=l} |g|^2, float;
+ *                   needs SLSHT_FP32_MIXED, n_omega <= 64 and
+ *                   ceil(((n_phi+1)/2)/16) * ceil(n_omega/16) <= 136.
  *  - Device pointers are HIP device memory owned by the caller; the library
  *    never frees them and keeps no reference after a call returns.  A
  *    `stream` argument is a hipStream_t (NULL = the default stream); work is
@@ -117,7 +118,8 @@ int64_t slsht_coupling_size(const slsht_desc* desc);
  * q(theta_b) of the discrete inverse (Section IV-A).  The plan owns that memory
  * and a coupling scratch of slsht_coupling_size() complex doubles.  Forward,
  * coupling and inverse calls on one plan share that scratch: issue them on one
- * stream, or use one plan per stream.  Synchronises the device before return. */
+ * stream, or use one plan per stream.  The tables are built on a private stream
+ * that is synchronised before return. */
 int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out);
 int slsht_plan_destroy(slsht_plan_t plan);
 /* Copy of the descriptor a plan was built from. */
