@@ -35,7 +35,8 @@
  *                   (SLSHT_FP64) or complex64 (SLSHT_FP32_MIXED).
  *    ENERGY output: E[l - l_lo][c][b - theta_lo][a] = sum_{|m|<=l} |g|^2, float;
  *                   needs SLSHT_FP32_MIXED, n_omega <= 64 and
- *                   ceil(((n_phi+1)/2)/16) * ceil(n_omega/16) <= 136.
+ *                   ceil(((n_phi+1)/2)/16) * T <= 136, T = ceil(n_omega/16)
+ *                   rounded up to 1, 2 or 4 (n_phi <= 1087 for n_omega > 32).
  *  - Device pointers are HIP device memory owned by the caller; the library
  *    never frees them and keeps no reference after a call returns.  A
  *    `stream` argument is a hipStream_t (NULL = the default stream); work is

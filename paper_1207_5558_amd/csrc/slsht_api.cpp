@@ -157,10 +157,12 @@ int check_desc(const slsht_desc* d) {
         if (d->n_omega > kEnergyMaxOmega)
             return set_error(SLSHT_EINVAL, "ENERGY output needs n_omega <= %d", kEnergyMaxOmega);
         const int nst = ((d->n_phi + 1) / 2 + 15) / 16, nct = (d->n_omega + 15) / 16;
-        if (nst * nct > kEnergyMaxTiles)
+        const int nctp = nct == 3 ? 4 : nct;      // omega tiles padded to divide the 8 waves
+        if (nst * nctp > kEnergyMaxTiles)
             return set_error(SLSHT_EINVAL,
-                             "ENERGY output needs ceil(((n_phi+1)/2)/16) * ceil(n_omega/16) <= %d "
-                             "(n_phi <= 1087 at n_omega = 64)", kEnergyMaxTiles);
+                             "ENERGY output needs ceil(((n_phi+1)/2)/16) * T <= %d with T = "
+                             "ceil(n_omega/16) rounded up to 1, 2 or 4 (n_phi <= 1087 at "
+                             "n_omega > 32)", kEnergyMaxTiles);
     }
     size_t out;
     const int64_t n_lm = (int64_t)d->l_hi * d->l_hi - (int64_t)d->l_lo * d->l_lo;

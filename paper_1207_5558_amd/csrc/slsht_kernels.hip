@@ -625,7 +625,7 @@ struct EnergyArgs {
     const float2* twfull;
     float* E;
     int64_t dstride;
-    int L, K, KP, l_lo, n_l, n_phi, n_omega, n_theta_out, nslot, ncp, nst, nct, cstride;
+    int L, K, KP, l_lo, n_l, n_phi, n_omega, n_theta_out, nslot, ncp, nst, nct, nctp, cstride;
     int real_pair, nblk;
 };
 
@@ -639,7 +639,11 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
     float2* h_s = A_s + L * L;
     float2* S_s = h_s + L * L;
     float* PMt = reinterpret_cast<float*>(S_s + KK);          // [4][KP][cstride]
-    float2* tw = reinterpret_cast<float2*>(PMt + 4 * KP * cs_);
+    float2* tw = reinterpret_cast<float2*>(PMt + 4 * KP * cs_);  // [n_phi] cos/sin(2 pi j/n_phi)
+    const int ncw = (a.ncp + 15) / 16 * 16;                      // omega slots, padded
+    const int nqt = (K + 15) / 16;                               // q tiles of the omega GEMM
+    float2* twW = tw + a.n_phi;                                  // [KP][ncw] cos/sin(k omega_cs)
+    float4* XY = reinterpret_cast<float4*>(twW + KP * ncw);      // [nqt*16][ncw] X, Y parts
     const int tid = threadIdx.x, nth = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
 
@@ -653,17 +657,23 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
 
     for (int i = tid; i < a.n_phi; i += nth) tw[i] = a.twfull[i];
     for (int i = tid; i < 4 * KP * cs_; i += nth) PMt[i] = 0.0f;
+    for (int i = tid; i < KP * ncw; i += nth) {
+        const int k = i / ncw, cs = i - k * ncw;
+        float2 v = vmk<float2>(0.0f, 0.0f);
+        if (cs < a.ncp && k < L) v = k == 0 ? vmk<float2>(1.0f, 0.0f) : a.twom[(k - 1) * a.ncp + cs];
+        twW[i] = v;
+    }
     for (int i = tid; i < L * L; i += nth) h_s[i] = vcast<float2>(a.h[i]);
 
-    // tile positions of this wave: p = wave + 16 j, slot tile p / nct, omega tile p % nct
+    // energy of this wave's tiles (omega tile w % nctp, slot tiles w / nctp + j * 8 / nctp)
     float Ep[TPW][4], Em[TPW][4];
 #pragma unroll
     for (int j = 0; j < TPW; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
-    const int ntp = a.nst * a.nct;
 
     const float* drow = a.dtab + (int64_t)t * a.dstride;
+    const int nrep = 2 * L * (L - 1) + 1;     // ring representatives of the K x K entries
     const int nm = a.real_pair ? l + 1 : 2 * l + 1;
     for (int mi = 0; mi < nm; ++mi) {
         const int m = a.real_pair ? mi : mi - l;
@@ -672,53 +682,109 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
         for (int i = tid; i < L * L; i += nth) A_s[i] = vcast<float2>(a.A[lm * L * L + i]);
         __syncthreads();
 
-        // stage 1: theta contraction
-        for (int idx = tid; idx < KK; idx += nth) {
-            const int qi = idx / K;
-            const int q = qi - (L - 1), qp = idx - qi * K - (L - 1);
-            const int aq = q < 0 ? -q : q, aqp = qp < 0 ? -qp : qp;
-            float sr = 0.0f, si = 0.0f;
-            for (int p = aq > aqp ? aq : aqp; p < L; ++p) {
-                const float dv = drow[dtab_off(p) + (q + p) * (2 * p + 1) + (qp + p)];
-                const float2 av = A_s[p * p + p + q], hv = h_s[p * p + p + qp];
-                sr += (av.x * hv.x - av.y * hv.y) * dv;
-                si += (av.x * hv.y + av.y * hv.x) * dv;
+        // stage 1: theta contraction, S_{q,q'} = sum_p A^p_q h^p_{q'} d^p_{q,q'}.  Entries are
+        // enumerated ring by ring (s = max(|q|,|q'|), so a wave's lanes share the trip count
+        // L - s), and each thread also produces the mirrored entry (-q,-q') from the same
+        // d values, d^p_{-q,-q'} = (-1)^{q-q'} d^p_{q,q'} (symmetry in Section IV-B).
+        for (int r = tid; r < nrep; r += nth) {
+            // representative r -> ring s and (q, q'): ring s (s >= 1) holds 4s
+            // representatives, q = -s (q' = -s..s) then q' = s (q = -s+1..s-1); rings are
+            // stored from s = L-1 down, ring 0 last
+            int s_, j;
+            if (r == nrep - 1) {
+                s_ = 0;
+                j = 0;
+            } else {
+                // reps before ring s: sum_{s' > s} 4 s' = 2 (L-1) L - 2 s (s+1)
+                const int x = 2 * (L - 1) * L - r;          // = 2 s (s+1) + (4s - j)
+                s_ = (int)((sqrtf(2.0f * (float)x + 1.0f) - 1.0f) * 0.5f);
+                while (2 * s_ * (s_ + 1) < x) ++s_;
+                while (s_ > 0 && 2 * (s_ - 1) * s_ >= x) --s_;
+                j = 2 * s_ * (s_ + 1) - x;                   // 0 <= j < 4 s
             }
-            S_s[idx] = vmk<float2>(sr, si);
+            int q, qp;
+            if (j <= 2 * s_) { q = -s_; qp = -s_ + j; }
+            else { qp = s_; q = -s_ + (j - 2 * s_); }
+            const float sgn = ((q - qp) & 1) ? -1.0f : 1.0f;
+            // degree-p offsets, advanced by additions
+            int off = dtab_off(s_) + (q + s_) * (2 * s_ + 1) + (qp + s_);
+            int ia = s_ * s_ + s_;                           // p^2 + p
+            float sr = 0.0f, si = 0.0f, tr = 0.0f, ti = 0.0f;
+            float dn = drow[off];
+            for (int p = s_; p < L; ++p) {
+                const float dv = dn;
+                const int nxt = off + (2 * p + 1) * (2 * p + 1) + 2 * q + 4 * p + 4;
+                if (p + 1 < L) dn = drow[nxt];
+                const float2 a1 = A_s[ia + q], h1 = h_s[ia + qp];
+                const float2 a2 = A_s[ia - q], h2 = h_s[ia - qp];
+                sr += (a1.x * h1.x - a1.y * h1.y) * dv;
+                si += (a1.x * h1.y + a1.y * h1.x) * dv;
+                tr += (a2.x * h2.x - a2.y * h2.y) * dv;
+                ti += (a2.x * h2.y + a2.y * h2.x) * dv;
+                off = nxt;
+                ia += 2 * p + 2;
+            }
+            S_s[(q + L - 1) * K + (qp + L - 1)] = vmk<float2>(sr, si);
+            if (s_ > 0) S_s[(L - 1 - q) * K + (L - 1 - qp)] = vmk<float2>(sgn * tr, sgn * ti);
         }
         __syncthreads();
 
-        // stage 2: omega synthesis into P_k, M_k (k = |q|), k-major, omega contiguous
-        for (int idx = tid; idx < a.ncp * L; idx += nth) {
-            const int cs = idx / L;
-            const int qa = idx - cs * L;
-            const float2* Sp = S_s + (qa + L - 1) * K;
-            const float2* Sm = S_s + (L - 1 - qa) * K;
-            float2 Xp = Sp[L - 1], Xm = Sm[L - 1];
-            float2 Yp = vmk<float2>(0, 0), Ym = vmk<float2>(0, 0);
-            for (int k = 1; k < L; ++k) {
-                const float2 tw2 = a.twom[(k - 1) * a.ncp + cs];
-                const float2 a1 = Sp[L - 1 + k], a2 = Sp[L - 1 - k];
-                const float2 b1 = Sm[L - 1 + k], b2 = Sm[L - 1 - k];
-                Xp.x += (a1.x + a2.x) * tw2.x; Xp.y += (a1.y + a2.y) * tw2.x;
-                Yp.x += (a1.x - a2.x) * tw2.y; Yp.y += (a1.y - a2.y) * tw2.y;
-                Xm.x += (b1.x + b2.x) * tw2.x; Xm.y += (b1.y + b2.y) * tw2.x;
-                Ym.x += (b1.x - b2.x) * tw2.y; Ym.y += (b1.y - b2.y) * tw2.y;
+        // stage 2: omega synthesis as folded real GEMMs on the MFMA units,
+        //   X[q][c] = S[q][0] + sum_{k>0} (S[q][k] + S[q][-k]) cos(k omega_c)
+        //   Y[q][c] =           sum_{k>0} (S[q][k] - S[q][-k]) sin(k omega_c)
+        // (Re and Im separately), one 16x16 (q, omega-slot) tile per wave and step.
+        for (int it = wave; it < nqt * (ncw / 16); it += kEnergyWaves) {
+            const int qt = it % nqt, ct2 = it / nqt;
+            const int kq2 = lane >> 4, c16 = lane & 15;
+            const int qi = qt * 16 + c16;
+            f4v xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0}, yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+            for (int kk = 0; kk < KP / 4; ++kk) {
+                const int k = kk * 4 + kq2;
+                float2 ap = vmk<float2>(0.0f, 0.0f), am = vmk<float2>(0.0f, 0.0f);
+                if (qi < K && k < L) {
+                    const float2* row = S_s + qi * K + (L - 1);
+                    if (k == 0) {
+                        ap = row[0];
+                    } else {
+                        const float2 s1 = row[k], s2 = row[-k];
+                        ap = vadd(s1, s2);
+                        am = vsub(s1, s2);
+                    }
+                }
+                const float2 w = twW[k * ncw + ct2 * 16 + c16];
+                xr = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.x, w.x, xr, 0, 0, 0);
+                xi = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.y, w.x, xi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(am.x, w.y, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(am.y, w.y, yi, 0, 0, 0);
             }
-            Yp = vmul_mi(Yp);
-            Ym = vmul_mi(Ym);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float4 v;
+                v.x = xr[r]; v.y = xi[r]; v.z = yr[r]; v.w = yi[r];
+                XY[(qt * 16 + 4 * kq2 + r) * ncw + ct2 * 16 + c16] = v;
+            }
+        }
+        __syncthreads();
+
+        // fold q = +-k: U_q(omega_c) = X + Y', U_q(omega_{n-c}) = X - Y' with Y' = -i Y, then
+        // P_k = U_k + U_{-k}, M_k = -i (U_k - U_{-k}); stored k-major, omega contiguous
+        for (int idx = tid; idx < L * a.ncp; idx += nth) {
+            const int qa = idx / a.ncp, cs = idx - qa * a.ncp;
+            const float4 vp = XY[(L - 1 + qa) * ncw + cs];
+            const float4 vm = XY[(L - 1 - qa) * ncw + cs];
             int c2 = a.n_omega - cs;
             if (cs == 0 || c2 == cs) c2 = -1;
             for (int side = 0; side < 2; ++side) {
                 const int c = side == 0 ? cs : c2;
                 if (c < 0) break;
-                const float2 Up = side == 0 ? vadd(Xp, Yp) : vsub(Xp, Yp);
+                const float sg = side == 0 ? 1.0f : -1.0f;
+                const float2 Up = vmk<float2>(vp.x + sg * vp.w, vp.y - sg * vp.z);
                 float2 P, M;
                 if (qa == 0) {
                     P = Up;
                     M = vmk<float2>(0, 0);
                 } else {
-                    const float2 Um = side == 0 ? vadd(Xm, Ym) : vsub(Xm, Ym);
+                    const float2 Um = vmk<float2>(vm.x + sg * vm.w, vm.y - sg * vm.z);
                     P = vadd(Up, Um);
                     M = vmul_mi(vsub(Up, Um));
                 }
@@ -730,36 +796,45 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
         }
         __syncthreads();
 
-        // stage 3: MFMA phi synthesis and energy accumulation.  The lane index is made
-        // opaque here so that the per-tile index arithmetic is redone for every m instead
-        // of being hoisted out of the m loop, where it would pin registers per tile.
+        // stage 3: MFMA phi synthesis and energy accumulation.  Wave w owns omega tile
+        // ct = w % nctp and slot tiles st = w / nctp + j * (waves / nctp), so its B fragments
+        // (P_k, M_k of that omega tile) are loaded once per m and stay in registers across
+        // all its slot tiles.  The lane index is made opaque so that the per-tile index
+        // arithmetic is redone for every m instead of being hoisted out of the m loop.
         int lane_o = lane;
         asm volatile("" : "+v"(lane_o));
         const int kq = lane_o >> 4, col = lane_o & 15;
+        const int nkk = KP / 4;
+        const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
+        float breg[4][8];
+        {
+            const int bcol = ct * 16 + col;
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = kk * 4 + kq;
+#pragma unroll
+                for (int part = 0; part < 4; ++part)
+                    breg[part][kk] = kk < nkk ? PMt[(part * KP + k) * cs_ + bcol] : 0.0f;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
-            const int p = wave + j * kEnergyWaves;
-            if (p >= ntp) break;
-            const int st = p / a.nct, ct = p - st * a.nct;
+            const int st = st0 + j * sstep;
+            if (st >= a.nst) break;
             const int as = st * 16 + col;                      // slot of this lane's A rows
             int step4 = 4 * as;                                // (4 as) mod n_phi, as < n_phi
             while (step4 >= a.n_phi) step4 -= a.n_phi;
             int idx = kq * as;                                 // (kq as) mod n_phi, kq < 4
             while (idx >= a.n_phi) idx -= a.n_phi;
             f4v cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0}, sre = {0, 0, 0, 0}, sim = {0, 0, 0, 0};
-            const int bcol = ct * 16 + col;
-#pragma unroll 2
-            for (int kk = 0; kk < KP / 4; ++kk) {
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                if (kk >= nkk) break;
                 const float2 cz = tw[idx];
-                const int k = kk * 4 + kq;
-                const float bpr = PMt[(0 * KP + k) * cs_ + bcol];
-                const float bpi = PMt[(1 * KP + k) * cs_ + bcol];
-                const float bmr = PMt[(2 * KP + k) * cs_ + bcol];
-                const float bmi = PMt[(3 * KP + k) * cs_ + bcol];
-                cre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, bpr, cre, 0, 0, 0);
-                cim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, bpi, cim, 0, 0, 0);
-                sre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, bmr, sre, 0, 0, 0);
-                sim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, bmi, sim, 0, 0, 0);
+                cre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, breg[0][kk], cre, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, breg[1][kk], cim, 0, 0, 0);
+                sre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, breg[2][kk], sre, 0, 0, 0);
+                sim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, breg[3][kk], sim, 0, 0, 0);
                 idx += step4;
                 if (idx >= a.n_phi) idx -= a.n_phi;
             }
@@ -781,11 +856,11 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
 
     // store: lane holds slots st*16 + 4*(lane/16) + r of omega column ct*16 + lane%16
     const int kq = lane >> 4, col = lane & 15;
+    const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-        const int p = wave + j * kEnergyWaves;
-        if (p >= ntp) break;
-        const int st = p / a.nct, ct = p - st * a.nct;
+        const int st = st0 + j * sstep;
+        if (st >= a.nst) break;
         const int c = ct * 16 + col;
         if (c >= a.n_omega) continue;
         float* row = a.E + (((int64_t)lidx * a.n_omega + c) * a.n_theta_out + t) * a.n_phi;
@@ -799,10 +874,19 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
     }
 }
 
+// Row stride (floats) of the k-major B table: at least nctp*16 columns, and
+// congruent to 16 mod 32 so that the 4 k rows a wave reads land on different banks.
+static int energy_cstride(int nctp) {
+    const int c = nctp * 16;
+    return c % 32 == 0 ? c + 16 : c;
+}
+
 static size_t energy_lds_bytes(const DevPlan& P, int KP, int cstride) {
     const int L = P.d.L_h, K = 2 * L - 1;
+    const int ncw = (P.d.n_omega / 2 + 1 + 15) / 16 * 16, nqt = (K + 15) / 16;
     return (size_t)(2 * L * L + K * K) * sizeof(float2) + (size_t)4 * KP * cstride * sizeof(float) +
-           (size_t)P.d.n_phi * sizeof(float2);
+           (size_t)P.d.n_phi * sizeof(float2) + (size_t)KP * ncw * sizeof(float2) +
+           (size_t)nqt * 16 * ncw * sizeof(float4);
 }
 
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
@@ -827,11 +911,13 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
     a.ncp = P.ncp_omega;
     a.nst = (P.nslot_phi + 15) / 16;
     a.nct = (P.d.n_omega + 15) / 16;
-    a.cstride = a.nct * 16 + ((a.nct * 16) % 32 == 0 ? 16 : 0);   // rows of k land on other banks
+    a.nctp = a.nct == 3 ? 4 : a.nct;                  // omega tiles padded to divide 8 waves
+    a.cstride = energy_cstride(a.nctp);
     a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     a.nblk = a.n_l * P.n_theta_out;
     const size_t lds = energy_lds_bytes(P, a.KP, a.cstride);
-    const int tpw = (a.nst * a.nct + kEnergyWaves - 1) / kEnergyWaves;
+    const int per = kEnergyWaves / a.nctp;           // waves sharing one omega tile
+    const int tpw = (a.nst + per - 1) / per;
     dim3 grid(a.nblk), block(64 * kEnergyWaves);
     if (lds > 64 * 1024) {
         const void* fns[] = {(const void*)energy_kernel<4>, (const void*)energy_kernel<8>,
@@ -850,7 +936,7 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
 size_t energy_lds_for(const DevPlan& P) {
     const int KP = (P.d.L_h + 3) / 4 * 4;
     const int nct = (P.d.n_omega + 15) / 16;
-    return energy_lds_bytes(P, KP, nct * 16 + ((nct * 16) % 32 == 0 ? 16 : 0));
+    return energy_lds_bytes(P, KP, energy_cstride(nct == 3 ? 4 : nct));
 }
 
 // ------------------------------------------------------------------------------
