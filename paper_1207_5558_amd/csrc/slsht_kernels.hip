@@ -320,6 +320,57 @@ hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipSt
 // same way.  Lane a of stage 3 keeps its cos/sin(q phi_a) in registers for all
 // rows; U_0, P_q, M_q are read as LDS broadcasts.
 
+// Theta-stage work items.  The K x K entries (q, q') of S are visited ring by ring,
+// s = max(|q|,|q'|) (every entry of ring s sums L - s degrees p, so lanes of a wave share
+// trip counts), and one item covers (q, q') and its mirror (-q, -q'), which reuses the
+// same d values: d^p_{-q,-q'} = (-1)^{q-q'} d^p_{q,q'} (symmetry in Section IV-B).
+// Ring s >= 1 has 4s items: q = -s (q' = -s..s), then q' = s (q = -s+1..s-1); rings are
+// stored from s = L-1 down to 1, and the last item is (0, 0) alone.
+__device__ __forceinline__ int ring_items(int L) { return 2 * L * (L - 1) + 1; }
+
+__device__ __forceinline__ void ring_item(int r, int L, int& s, int& q, int& qp) {
+    int j;
+    if (r == ring_items(L) - 1) {
+        s = 0;
+        j = 0;
+    } else {
+        const int x = 2 * (L - 1) * L - r;          // = 2 s (s+1) + (4s - j), 0 <= j < 4s
+        s = (int)((sqrtf(2.0f * (float)x + 1.0f) - 1.0f) * 0.5f);
+        while (2 * s * (s + 1) < x) ++s;
+        while (s > 0 && 2 * (s - 1) * s >= x) --s;
+        j = 2 * s * (s + 1) - x;
+    }
+    if (j <= 2 * s) { q = -s; qp = -s + j; }
+    else { qp = s; q = -s + (j - 2 * s); }
+}
+
+// S_{q,q'} and S_{-q,-q'} of one theta row for the ring item (s, q, q'): offsets into the
+// Wigner-d row advance by additions and the next d value is loaded one step ahead.
+template <typename T, typename V>
+__device__ __forceinline__ void theta_pair(const T* __restrict__ drow, const V* A_s, const V* h_s,
+                                           int L, int s, int q, int qp, V& out, V& mirror) {
+    int off = dtab_off(s) + (q + s) * (2 * s + 1) + (qp + s);
+    int ia = s * s + s;                              // p^2 + p
+    T sr = 0, si = 0, tr = 0, ti = 0;
+    T dn = drow[off];
+    for (int p = s; p < L; ++p) {
+        const T dv = dn;
+        const int nxt = off + (2 * p + 1) * (2 * p + 1) + 2 * q + 4 * p + 4;
+        if (p + 1 < L) dn = drow[nxt];
+        const V a1 = A_s[ia + q], h1 = h_s[ia + qp];
+        const V a2 = A_s[ia - q], h2 = h_s[ia - qp];
+        sr += (a1.x * h1.x - a1.y * h1.y) * dv;
+        si += (a1.x * h1.y + a1.y * h1.x) * dv;
+        tr += (a2.x * h2.x - a2.y * h2.y) * dv;
+        ti += (a2.x * h2.y + a2.y * h2.x) * dv;
+        off = nxt;
+        ia += 2 * p + 2;
+    }
+    const T sgn = ((q - qp) & 1) ? T(-1) : T(1);
+    out = vmk<V>(sr, si);
+    mirror = vmk<V>(sgn * tr, sgn * ti);
+}
+
 struct SynthArgs {
     const double2* A;
     const double2* h;
@@ -329,6 +380,7 @@ struct SynthArgs {
     void* g;
     int64_t dstride;
     int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp, l_lo, real_pair;
+    int xsize;    // elements of the A/h | P/M union region in LDS
 };
 
 // Synthesis item -> output slot lm, degree l, order m and the slot of order -m that is
@@ -367,6 +419,7 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     V* A_s = X_s;
     V* h_s = X_s + LH * LH;
     V* PM_s = X_s;                       // [t][c][2][LH], reuses the A/h space
+    V* TW_s = X_s + a.xsize;             // [L-1][ncp] omega twiddles
 
     const int item = blockIdx.x / a.n_tiles;
     const int tile = blockIdx.x - item * a.n_tiles;
@@ -375,36 +428,31 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     const int tb = min(a.tb, a.n_theta_out - t0);
     const int tid = threadIdx.x, nth = blockDim.x;
 
+    const V* twg = reinterpret_cast<const V*>(a.twom);
     for (int i = tid; i < L * L; i += nth) {
         A_s[i] = vcast<V>(a.A[(int64_t)it.lm * L * L + i]);
         h_s[i] = vcast<V>(a.h[i]);
     }
+    for (int i = tid; i < (L - 1) * a.ncp; i += nth) TW_s[i] = twg[i];
     __syncthreads();
 
-    // stage 1: theta contraction
+    // stage 1: theta contraction, ring-ordered items (see ring_item / theta_pair)
     const T* dt = reinterpret_cast<const T*>(a.dtab);
     const int KK = K * K;
-    for (int idx = tid; idx < tb * KK; idx += nth) {
-        const int t = idx / KK;
-        const int r = idx - t * KK;
-        const int qi = r / K;
-        const int q = qi - (L - 1), qp = r - qi * K - (L - 1);
-        const int aq = q < 0 ? -q : q, aqp = qp < 0 ? -qp : qp;
-        const T* drow = dt + (int64_t)(t0 + t) * a.dstride;
-        T sr = 0, si = 0;
-        for (int p = aq > aqp ? aq : aqp; p < L; ++p) {
-            const T dv = drow[dtab_off(p) + (q + p) * (2 * p + 1) + (qp + p)];
-            const V av = A_s[p * p + p + q], hv = h_s[p * p + p + qp];
-            const T pr = av.x * hv.x - av.y * hv.y, pi = av.x * hv.y + av.y * hv.x;
-            sr += pr * dv;
-            si += pi * dv;
-        }
-        S_s[idx] = vmk<V>(sr, si);
+    const int nrep = ring_items(L);
+    for (int idx = tid; idx < tb * nrep; idx += nth) {
+        const int t = idx / nrep;
+        int s_, q, qp;
+        ring_item(idx - t * nrep, L, s_, q, qp);
+        V v, vm;
+        theta_pair<T, V>(dt + (int64_t)(t0 + t) * a.dstride, A_s, h_s, L, s_, q, qp, v, vm);
+        S_s[t * KK + (q + L - 1) * K + (qp + L - 1)] = v;
+        if (s_ > 0) S_s[t * KK + (L - 1 - q) * K + (L - 1 - qp)] = vm;
     }
     __syncthreads();
 
     // stage 2: omega synthesis, folded into P/M
-    const V* twom = reinterpret_cast<const V*>(a.twom);
+    const V* twom = TW_s;
     const int per_t = a.ncp * L;
     for (int idx = tid; idx < tb * per_t; idx += nth) {
         const int t = idx / per_t;
@@ -523,12 +571,17 @@ static int ns_max(bool f64, int LH) {
     return LH <= 8 ? 4 : (LH == 16 ? 2 : 1);
 }
 
+static size_t synth_xsize(const DevPlan& P, int tb) {
+    const int LH = lh_bucket(P.d.L_h);
+    return std::max((size_t)2 * LH * LH, (size_t)tb * P.d.n_omega * 2 * LH);
+}
+
 static size_t synth_lds_bytes(const DevPlan& P, int tb) {
-    const int L = P.d.L_h, K = 2 * L - 1, LH = lh_bucket(L);
+    const int L = P.d.L_h, K = 2 * L - 1;
     const size_t v = P.d.precision == SLSHT_FP64 ? 16 : 8;
     const size_t s = (size_t)tb * K * K;
-    const size_t x = std::max((size_t)2 * LH * LH, (size_t)tb * P.d.n_omega * 2 * LH);
-    return (s + x) * v;
+    const size_t tw = (size_t)(L > 1 ? L - 1 : 0) * (P.d.n_omega / 2 + 1);
+    return (s + synth_xsize(P, tb) + tw) * v;
 }
 
 bool choose_synthesis_shape(DevPlan& P, size_t lds_limit) {
@@ -591,6 +644,7 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
     a.ncp = P.ncp_omega;
     a.l_lo = P.d.l_lo;
     a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
+    a.xsize = (int)synth_xsize(P, P.tb);
     const bool f64 = P.d.precision == SLSHT_FP64;
     switch (lh_bucket(P.d.L_h)) {
         case 4: return f64 ? launch_synth_t<double, 4>(P, a, s) : launch_synth_t<float, 4>(P, a, s);
@@ -673,7 +727,7 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
         for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
 
     const float* drow = a.dtab + (int64_t)t * a.dstride;
-    const int nrep = 2 * L * (L - 1) + 1;     // ring representatives of the K x K entries
+    const int nrep = ring_items(L);
     const int nm = a.real_pair ? l + 1 : 2 * l + 1;
     for (int mi = 0; mi < nm; ++mi) {
         const int m = a.real_pair ? mi : mi - l;
@@ -682,50 +736,14 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
         for (int i = tid; i < L * L; i += nth) A_s[i] = vcast<float2>(a.A[lm * L * L + i]);
         __syncthreads();
 
-        // stage 1: theta contraction, S_{q,q'} = sum_p A^p_q h^p_{q'} d^p_{q,q'}.  Entries are
-        // enumerated ring by ring (s = max(|q|,|q'|), so a wave's lanes share the trip count
-        // L - s), and each thread also produces the mirrored entry (-q,-q') from the same
-        // d values, d^p_{-q,-q'} = (-1)^{q-q'} d^p_{q,q'} (symmetry in Section IV-B).
+        // stage 1: theta contraction, ring-ordered items (see ring_item / theta_pair)
         for (int r = tid; r < nrep; r += nth) {
-            // representative r -> ring s and (q, q'): ring s (s >= 1) holds 4s
-            // representatives, q = -s (q' = -s..s) then q' = s (q = -s+1..s-1); rings are
-            // stored from s = L-1 down, ring 0 last
-            int s_, j;
-            if (r == nrep - 1) {
-                s_ = 0;
-                j = 0;
-            } else {
-                // reps before ring s: sum_{s' > s} 4 s' = 2 (L-1) L - 2 s (s+1)
-                const int x = 2 * (L - 1) * L - r;          // = 2 s (s+1) + (4s - j)
-                s_ = (int)((sqrtf(2.0f * (float)x + 1.0f) - 1.0f) * 0.5f);
-                while (2 * s_ * (s_ + 1) < x) ++s_;
-                while (s_ > 0 && 2 * (s_ - 1) * s_ >= x) --s_;
-                j = 2 * s_ * (s_ + 1) - x;                   // 0 <= j < 4 s
-            }
-            int q, qp;
-            if (j <= 2 * s_) { q = -s_; qp = -s_ + j; }
-            else { qp = s_; q = -s_ + (j - 2 * s_); }
-            const float sgn = ((q - qp) & 1) ? -1.0f : 1.0f;
-            // degree-p offsets, advanced by additions
-            int off = dtab_off(s_) + (q + s_) * (2 * s_ + 1) + (qp + s_);
-            int ia = s_ * s_ + s_;                           // p^2 + p
-            float sr = 0.0f, si = 0.0f, tr = 0.0f, ti = 0.0f;
-            float dn = drow[off];
-            for (int p = s_; p < L; ++p) {
-                const float dv = dn;
-                const int nxt = off + (2 * p + 1) * (2 * p + 1) + 2 * q + 4 * p + 4;
-                if (p + 1 < L) dn = drow[nxt];
-                const float2 a1 = A_s[ia + q], h1 = h_s[ia + qp];
-                const float2 a2 = A_s[ia - q], h2 = h_s[ia - qp];
-                sr += (a1.x * h1.x - a1.y * h1.y) * dv;
-                si += (a1.x * h1.y + a1.y * h1.x) * dv;
-                tr += (a2.x * h2.x - a2.y * h2.y) * dv;
-                ti += (a2.x * h2.y + a2.y * h2.x) * dv;
-                off = nxt;
-                ia += 2 * p + 2;
-            }
-            S_s[(q + L - 1) * K + (qp + L - 1)] = vmk<float2>(sr, si);
-            if (s_ > 0) S_s[(L - 1 - q) * K + (L - 1 - qp)] = vmk<float2>(sgn * tr, sgn * ti);
+            int s_, q, qp;
+            ring_item(r, L, s_, q, qp);
+            float2 v, vm;
+            theta_pair<float, float2>(drow, A_s, h_s, L, s_, q, qp, v, vm);
+            S_s[(q + L - 1) * K + (qp + L - 1)] = v;
+            if (s_ > 0) S_s[(L - 1 - q) * K + (L - 1 - qp)] = vm;
         }
         __syncthreads();
 
