@@ -35,8 +35,12 @@ def log(msg):
 
 
 def kernel_source_digest() -> str:
-    p = os.path.join(ROOT, "paper_1207_5558_amd", "csrc", "slsht_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Digest of the sources of the FULL synthesis kernel (its file and the device
+    helpers it includes); a counter summary is used only if it carries the same one."""
+    h = hashlib.sha256()
+    for name in ("slsht_synth.hip", "slsht_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1207_5558_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def committed_traffic(profile_name: str, digest: str):

@@ -1,0 +1,313 @@
+// gfx950 kernel K3e of the directional SLSHT forward path: the ENERGY output
+// E(rho; l) = sum_m |g(rho; l, m)|^2, reduced over the orders m on the fly.
+#include "slsht_device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+namespace slsht {
+
+// ------------------------------------------------------------------------------
+// K3e: energy epilogue, FP32.  One block = one degree l x one theta row; the order m
+// runs inside the block and E(phi_a, theta_b, omega_c; l) = sum_m |g|^2 stays in
+// registers until all orders are done, so g is never written.  Per m:
+//   stage 1 (VALU): S_{q,q'}(theta_b) as in K3                              -> LDS
+//   stage 2 (VALU): omega synthesis folded into P_k, M_k, stored k-major with
+//                   omega contiguous (the B operand layout of the MFMA below)  -> LDS
+//   stage 3 (MFMA): the phi synthesis is a real GEMM per part (Re, Im) and per
+//                   cos/sin half:  C[a][c] = sum_k cos(k phi_a) P_k(c),
+//                   S[a][c] = sum_k sin(k phi_a) M_k(c)   (16x16x4 FP32 MFMA),
+//                   then E(a) += |C+S|^2 and E(n-a) += |C-S|^2 elementwise.
+// A fragments (cos/sin(k phi_a)) come from an n_phi-entry cos/sin table in LDS at
+// index k*a mod n_phi, advanced incrementally.  Lane l of a 16x16x4 FP32 MFMA
+// supplies A[l%16][l/16] and B[l/16][l%16] and receives D rows 4*(l/16)+r, column l%16.
+
+struct EnergyArgs {
+    const double2* A;
+    const double2* h;
+    const float* dtab;
+    const float2* twom;
+    const float2* twfull;
+    float* E;
+    int64_t dstride;
+    int L, K, KP, l_lo, n_l, n_phi, n_omega, n_theta_out, nslot, ncp, nst, nct, nctp, cstride;
+    int real_pair, nblk;
+};
+
+constexpr int kEnergyWaves = 8;
+
+template <int TPW>
+__global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L = a.L, K = a.K, KK = K * K, KP = a.KP, cs_ = a.cstride;
+    float2* A_s = reinterpret_cast<float2*>(smem_raw);
+    float2* h_s = A_s + L * L;
+    float2* S_s = h_s + L * L;
+    float* PMt = reinterpret_cast<float*>(S_s + KK);          // [4][KP][cstride]
+    float2* tw = reinterpret_cast<float2*>(PMt + 4 * KP * cs_);  // [n_phi] cos/sin(2 pi j/n_phi)
+    const int ncw = (a.ncp + 15) / 16 * 16;                      // omega slots, padded
+    const int nqt = (K + 15) / 16;                               // q tiles of the omega GEMM
+    float2* twW = tw + a.n_phi;                                  // [KP][ncw] cos/sin(k omega_cs)
+    float4* XY = reinterpret_cast<float4*>(twW + KP * ncw);      // [nqt*16][ncw] X, Y parts
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    // XCD-aware order: consecutive logical blocks (same theta row, other degrees) land
+    // on one XCD and share its L2 copy of the Wigner-d row.
+    int bid = blockIdx.x;
+    if ((a.nblk & 7) == 0) bid = (blockIdx.x & 7) * (a.nblk >> 3) + (blockIdx.x >> 3);
+    const int t = bid / a.n_l;
+    const int lidx = bid - t * a.n_l;
+    const int l = a.l_lo + lidx;
+
+    for (int i = tid; i < a.n_phi; i += nth) tw[i] = a.twfull[i];
+    for (int i = tid; i < 4 * KP * cs_; i += nth) PMt[i] = 0.0f;
+    for (int i = tid; i < KP * ncw; i += nth) {
+        const int k = i / ncw, cs = i - k * ncw;
+        float2 v = vmk<float2>(0.0f, 0.0f);
+        if (cs < a.ncp && k < L) v = k == 0 ? vmk<float2>(1.0f, 0.0f) : a.twom[(k - 1) * a.ncp + cs];
+        twW[i] = v;
+    }
+    for (int i = tid; i < L * L; i += nth) h_s[i] = vcast<float2>(a.h[i]);
+
+    // energy of this wave's tiles (omega tile w % nctp, slot tiles w / nctp + j * 8 / nctp)
+    float Ep[TPW][4], Em[TPW][4];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
+
+    const float* drow = a.dtab + (int64_t)t * a.dstride;
+    const int nrep = ring_items(L);
+    const int nm = a.real_pair ? l + 1 : 2 * l + 1;
+    for (int mi = 0; mi < nm; ++mi) {
+        const int m = a.real_pair ? mi : mi - l;
+        const float wgt = (a.real_pair && m > 0) ? 2.0f : 1.0f;
+        const int64_t lm = (int64_t)l * l + l + m - (int64_t)a.l_lo * a.l_lo;
+        for (int i = tid; i < L * L; i += nth) A_s[i] = vcast<float2>(a.A[lm * L * L + i]);
+        __syncthreads();
+
+        // stage 1: theta contraction, ring-ordered items (see ring_item / theta_pair)
+        for (int r = tid; r < nrep; r += nth) {
+            int s_, q, qp;
+            ring_item(r, L, s_, q, qp);
+            float2 v, vm;
+            theta_pair<float, float2, 8>(drow, A_s, h_s, L, s_, q, qp, v, vm);
+            S_s[(q + L - 1) * K + (qp + L - 1)] = v;
+            if (s_ > 0) S_s[(L - 1 - q) * K + (L - 1 - qp)] = vm;
+        }
+        __syncthreads();
+
+        // stage 2: omega synthesis as folded real GEMMs on the MFMA units,
+        //   X[q][c] = S[q][0] + sum_{k>0} (S[q][k] + S[q][-k]) cos(k omega_c)
+        //   Y[q][c] =           sum_{k>0} (S[q][k] - S[q][-k]) sin(k omega_c)
+        // (Re and Im separately), one 16x16 (q, omega-slot) tile per wave and step.
+        for (int it = wave; it < nqt * (ncw / 16); it += kEnergyWaves) {
+            const int qt = it % nqt, ct2 = it / nqt;
+            const int kq2 = lane >> 4, c16 = lane & 15;
+            const int qi = qt * 16 + c16;
+            f4v xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0}, yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+            for (int kk = 0; kk < KP / 4; ++kk) {
+                const int k = kk * 4 + kq2;
+                float2 ap = vmk<float2>(0.0f, 0.0f), am = vmk<float2>(0.0f, 0.0f);
+                if (qi < K && k < L) {
+                    const float2* row = S_s + qi * K + (L - 1);
+                    if (k == 0) {
+                        ap = row[0];
+                    } else {
+                        const float2 s1 = row[k], s2 = row[-k];
+                        ap = vadd(s1, s2);
+                        am = vsub(s1, s2);
+                    }
+                }
+                const float2 w = twW[k * ncw + ct2 * 16 + c16];
+                xr = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.x, w.x, xr, 0, 0, 0);
+                xi = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.y, w.x, xi, 0, 0, 0);
+                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(am.x, w.y, yr, 0, 0, 0);
+                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(am.y, w.y, yi, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float4 v;
+                v.x = xr[r]; v.y = xi[r]; v.z = yr[r]; v.w = yi[r];
+                XY[(qt * 16 + 4 * kq2 + r) * ncw + ct2 * 16 + c16] = v;
+            }
+        }
+        __syncthreads();
+
+        // fold q = +-k: U_q(omega_c) = X + Y', U_q(omega_{n-c}) = X - Y' with Y' = -i Y, then
+        // P_k = U_k + U_{-k}, M_k = -i (U_k - U_{-k}); stored k-major, omega contiguous
+        for (int idx = tid; idx < L * a.ncp; idx += nth) {
+            const int qa = idx / a.ncp, cs = idx - qa * a.ncp;
+            const float4 vp = XY[(L - 1 + qa) * ncw + cs];
+            const float4 vm = XY[(L - 1 - qa) * ncw + cs];
+            int c2 = a.n_omega - cs;
+            if (cs == 0 || c2 == cs) c2 = -1;
+            for (int side = 0; side < 2; ++side) {
+                const int c = side == 0 ? cs : c2;
+                if (c < 0) break;
+                const float sg = side == 0 ? 1.0f : -1.0f;
+                const float2 Up = vmk<float2>(vp.x + sg * vp.w, vp.y - sg * vp.z);
+                float2 P, M;
+                if (qa == 0) {
+                    P = Up;
+                    M = vmk<float2>(0, 0);
+                } else {
+                    const float2 Um = vmk<float2>(vm.x + sg * vm.w, vm.y - sg * vm.z);
+                    P = vadd(Up, Um);
+                    M = vmul_mi(vsub(Up, Um));
+                }
+                PMt[(0 * KP + qa) * cs_ + c] = P.x;
+                PMt[(1 * KP + qa) * cs_ + c] = P.y;
+                PMt[(2 * KP + qa) * cs_ + c] = M.x;
+                PMt[(3 * KP + qa) * cs_ + c] = M.y;
+            }
+        }
+        __syncthreads();
+
+        // stage 3: MFMA phi synthesis and energy accumulation.  Wave w owns omega tile
+        // ct = w % nctp and slot tiles st = w / nctp + j * (waves / nctp), so its B fragments
+        // (P_k, M_k of that omega tile) are loaded once per m and stay in registers across
+        // all its slot tiles.  The lane index is made opaque so that the per-tile index
+        // arithmetic is redone for every m instead of being hoisted out of the m loop.
+        int lane_o = lane;
+        asm volatile("" : "+v"(lane_o));
+        const int kq = lane_o >> 4, col = lane_o & 15;
+        const int nkk = KP / 4;
+        const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
+        float breg[4][8];
+        {
+            const int bcol = ct * 16 + col;
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = kk * 4 + kq;
+#pragma unroll
+                for (int part = 0; part < 4; ++part)
+                    breg[part][kk] = kk < nkk ? PMt[(part * KP + k) * cs_ + bcol] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int st = st0 + j * sstep;
+            if (st >= a.nst) break;
+            const int as = st * 16 + col;                      // slot of this lane's A rows
+            int step4 = 4 * as;                                // (4 as) mod n_phi, as < n_phi
+            while (step4 >= a.n_phi) step4 -= a.n_phi;
+            int idx = kq * as;                                 // (kq as) mod n_phi, kq < 4
+            while (idx >= a.n_phi) idx -= a.n_phi;
+            f4v cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0}, sre = {0, 0, 0, 0}, sim = {0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                if (kk >= nkk) break;
+                const float2 cz = tw[idx];
+                cre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, breg[0][kk], cre, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, breg[1][kk], cim, 0, 0, 0);
+                sre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, breg[2][kk], sre, 0, 0, 0);
+                sim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, breg[3][kk], sim, 0, 0, 0);
+                idx += step4;
+                if (idx >= a.n_phi) idx -= a.n_phi;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float pr = cre[r] + sre[r], pi = cim[r] + sim[r];
+                const float mr = cre[r] - sre[r], mi2 = cim[r] - sim[r];
+                Ep[j][r] += wgt * (pr * pr + pi * pi);
+                Em[j][r] += wgt * (mr * mr + mi2 * mi2);
+            }
+            // Materialise this tile's energy here, so that its four MFMA accumulators die
+            // before the next tile starts (otherwise the updates sink to the end of the
+            // unrolled loop and every tile's accumulators stay live at once).
+            asm volatile("" : "+v"(Ep[j][0]), "+v"(Ep[j][1]), "+v"(Ep[j][2]), "+v"(Ep[j][3]),
+                         "+v"(Em[j][0]), "+v"(Em[j][1]), "+v"(Em[j][2]), "+v"(Em[j][3]));
+        }
+        __syncthreads();
+    }
+
+    // store: lane holds slots st*16 + 4*(lane/16) + r of omega column ct*16 + lane%16
+    const int kq = lane >> 4, col = lane & 15;
+    const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int st = st0 + j * sstep;
+        if (st >= a.nst) break;
+        const int c = ct * 16 + col;
+        if (c >= a.n_omega) continue;
+        float* row = a.E + (((int64_t)lidx * a.n_omega + c) * a.n_theta_out + t) * a.n_phi;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int s = st * 16 + 4 * kq + r;
+            if (s >= a.nslot) continue;
+            row[s] = Ep[j][r];
+            if (s > 0) row[a.n_phi - s] = Em[j][r];
+        }
+    }
+}
+
+// Row stride (floats) of the k-major B table: at least nctp*16 columns, and
+// congruent to 16 mod 32 so that the 4 k rows a wave reads land on different banks.
+static int energy_cstride(int nctp) {
+    const int c = nctp * 16;
+    return c % 32 == 0 ? c + 16 : c;
+}
+
+static size_t energy_lds_bytes(const DevPlan& P, int KP, int cstride) {
+    const int L = P.d.L_h, K = 2 * L - 1;
+    const int ncw = (P.d.n_omega / 2 + 1 + 15) / 16 * 16, nqt = (K + 15) / 16;
+    return (size_t)(2 * L * L + K * K) * sizeof(float2) + (size_t)4 * KP * cstride * sizeof(float) +
+           (size_t)P.d.n_phi * sizeof(float2) + (size_t)KP * ncw * sizeof(float2) +
+           (size_t)nqt * 16 * ncw * sizeof(float4);
+}
+
+hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
+                         hipStream_t s) {
+    EnergyArgs a;
+    a.A = A;
+    a.h = h;
+    a.dtab = reinterpret_cast<const float*>(P.T->dtab);
+    a.twom = reinterpret_cast<const float2*>(P.T->tw_omega);
+    a.twfull = reinterpret_cast<const float2*>(P.T->tw_full);
+    a.E = E;
+    a.dstride = dtab_row_len(P.d.L_h);
+    a.L = P.d.L_h;
+    a.K = 2 * P.d.L_h - 1;
+    a.KP = (P.d.L_h + 3) / 4 * 4;
+    a.l_lo = P.d.l_lo;
+    a.n_l = P.d.l_hi - P.d.l_lo;
+    a.n_phi = P.d.n_phi;
+    a.n_omega = P.d.n_omega;
+    a.n_theta_out = P.n_theta_out;
+    a.nslot = P.nslot_phi;
+    a.ncp = P.ncp_omega;
+    a.nst = (P.nslot_phi + 15) / 16;
+    a.nct = (P.d.n_omega + 15) / 16;
+    a.nctp = a.nct == 3 ? 4 : a.nct;                  // omega tiles padded to divide 8 waves
+    a.cstride = energy_cstride(a.nctp);
+    a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
+    a.nblk = a.n_l * P.n_theta_out;
+    const size_t lds = energy_lds_bytes(P, a.KP, a.cstride);
+    const int per = kEnergyWaves / a.nctp;           // waves sharing one omega tile
+    const int tpw = (a.nst + per - 1) / per;
+    dim3 grid(a.nblk), block(64 * kEnergyWaves);
+    if (lds > 64 * 1024) {
+        const void* fns[] = {(const void*)energy_kernel<4>, (const void*)energy_kernel<8>,
+                             (const void*)energy_kernel<12>, (const void*)energy_kernel<17>};
+        for (const void* fn : fns)
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    if (tpw <= 4) hipLaunchKernelGGL(energy_kernel<4>, grid, block, lds, s, a);
+    else if (tpw <= 8) hipLaunchKernelGGL(energy_kernel<8>, grid, block, lds, s, a);
+    else if (tpw <= 12) hipLaunchKernelGGL(energy_kernel<12>, grid, block, lds, s, a);
+    else if (tpw <= 17) hipLaunchKernelGGL(energy_kernel<17>, grid, block, lds, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+size_t energy_lds_for(const DevPlan& P) {
+    const int KP = (P.d.L_h + 3) / 4 * 4;
+    const int nct = (P.d.n_omega + 15) / 16;
+    return energy_lds_bytes(P, KP, energy_cstride(nct == 3 ? 4 : nct));
+}
+
+}  // namespace slsht
