@@ -254,7 +254,7 @@ def main():
     # algorithmic bytes of the synthesis kernel per launch: the output written once, plus
     # the Wigner-d table, coupling coefficients, window and twiddles read once
     L = wl.L_h
-    table_bytes = wl.n_theta * (L * (4 * L * L - 1) // 3) * 8
+    table_bytes = wl.n_theta * (L * (L + 1) * (2 * L + 1) // 6) * 8     # canonical d entries
     in_bytes = wl.n_lm * L * L * 16 + L * L * 16 + table_bytes
     alg_bytes = r["out_bytes"] + in_bytes
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9

@@ -62,44 +62,63 @@ __device__ __forceinline__ void ring_item(int r, int L, int& s, int& q, int& qp)
     else { qp = s; q = -s + (j - 2 * s); }
 }
 
-// S_{q,q'} and S_{-q,-q'} of one theta row for the ring item (s, q, q').  Offsets into
-// the Wigner-d row advance by additions; the d values of PF consecutive degrees are
-// loaded together before they are used, so an item waits for memory ceil((L-s)/PF)
-// times rather than L-s times.
+// Canonical table entry of d^p_{q,q'}: d_{q,q'} = sign * d_{Q,Q'} with Q = max(|q|,|q'|)
+// >= |Q'|, from d_{q,q'} = (-1)^{q-q'} d_{q',q} = d_{-q',-q} (symmetries of Section IV-B).
+__device__ __forceinline__ void d_canonical(int q, int qp, int& Q, int& Qp, bool& neg) {
+    const int aq = q < 0 ? -q : q, aqp = qp < 0 ? -qp : qp;
+    const bool odd = ((q - qp) & 1) != 0;
+    if (aq >= aqp) {
+        if (q >= 0) { Q = q; Qp = qp; neg = false; }
+        else { Q = -q; Qp = -qp; neg = odd; }
+    } else {
+        if (qp > 0) { Q = qp; Qp = q; neg = odd; }
+        else { Q = -qp; Qp = -q; neg = false; }
+    }
+}
+
+// S_{q,q'} and S_{-q,-q'} of one theta row for the ring item (s, q, q'), from the
+// canonical Wigner-d row (global memory or LDS).  Offsets into the row advance by
+// additions; the d, A and h values of PF consecutive degrees are loaded together before
+// they are used, so an item waits for memory ceil((L-s)/PF) times rather than L-s times.
 template <typename T, typename V, int PF>
 __device__ __forceinline__ void theta_pair(const T* __restrict__ drow, const V* A_s, const V* h_s,
                                            int L, int s, int q, int qp, V& out, V& mirror) {
-    int off = dtab_off(s) + (q + s) * (2 * s + 1) + (qp + s);
-    int ia = s * s + s;                              // p^2 + p
+    int Q, Qp;
+    bool neg;
+    d_canonical(q, qp, Q, Qp, neg);                  // Q == s
+    int off = dtab_off(s) + Q * Q + Q + Qp;
     T sr = 0, si = 0, tr = 0, ti = 0;
     for (int p0 = s; p0 < L; p0 += PF) {
+        // all loads of PF degrees first, branch-free: degrees past L read valid entries
+        // (of degree L-1) and are weighted by zero
         T dv[PF];
+        V a1[PF], h1[PF], a2[PF], h2[PF];
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int p = p0 + i;
-            dv[i] = 0;
-            if (p < L) {
-                dv[i] = drow[off];
-                off += (2 * p + 1) * (2 * p + 1) + 2 * q + 4 * p + 4;
-            }
+            const bool ok = p < L;
+            const int pe = ok ? p : L - 1;
+            const int ia = pe * pe + pe;
+            const T x = drow[ok ? off : 0];
+            dv[i] = ok ? x : T(0);
+            a1[i] = A_s[ia + q];
+            h1[i] = h_s[ia + qp];
+            a2[i] = A_s[ia - q];
+            h2[i] = h_s[ia - qp];
+            off += (p + 1) * (p + 1);
         }
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
-            const int p = p0 + i;
-            if (p < L) {
-                const V a1 = A_s[ia + q], h1 = h_s[ia + qp];
-                const V a2 = A_s[ia - q], h2 = h_s[ia - qp];
-                sr += (a1.x * h1.x - a1.y * h1.y) * dv[i];
-                si += (a1.x * h1.y + a1.y * h1.x) * dv[i];
-                tr += (a2.x * h2.x - a2.y * h2.y) * dv[i];
-                ti += (a2.x * h2.y + a2.y * h2.x) * dv[i];
-                ia += 2 * p + 2;
-            }
+            sr += (a1[i].x * h1[i].x - a1[i].y * h1[i].y) * dv[i];
+            si += (a1[i].x * h1[i].y + a1[i].y * h1[i].x) * dv[i];
+            tr += (a2[i].x * h2[i].x - a2[i].y * h2[i].y) * dv[i];
+            ti += (a2[i].x * h2[i].y + a2[i].y * h2[i].x) * dv[i];
         }
     }
-    const T sgn = ((q - qp) & 1) ? T(-1) : T(1);
-    out = vmk<V>(sr, si);
-    mirror = vmk<V>(sgn * tr, sgn * ti);
+    const T sg = neg ? T(-1) : T(1);
+    const T sgm = ((q - qp) & 1) ? -sg : sg;
+    out = vmk<V>(sg * sr, sg * si);
+    mirror = vmk<V>(sgm * tr, sgm * ti);
 }
 
 }  // namespace slsht

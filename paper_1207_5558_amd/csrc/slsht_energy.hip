@@ -38,19 +38,23 @@ struct EnergyArgs {
 
 constexpr int kEnergyWaves = 8;
 
-template <int TPW>
+// TPW: slot tiles per wave; NKK >= KP/4: k-steps of the MFMA loops, a compile-time bound
+// so that the loops unroll and every A fragment of a tile is loaded before its MFMAs.
+template <int TPW, int NKK>
 __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int L = a.L, K = a.K, KK = K * K, KP = a.KP, cs_ = a.cstride;
-    float2* A_s = reinterpret_cast<float2*>(smem_raw);
-    float2* h_s = A_s + L * L;
-    float2* S_s = h_s + L * L;
-    float* PMt = reinterpret_cast<float*>(S_s + KK);          // [4][KP][cstride]
-    float2* tw = reinterpret_cast<float2*>(PMt + 4 * KP * cs_);  // [n_phi] cos/sin(2 pi j/n_phi)
     const int ncw = (a.ncp + 15) / 16 * 16;                      // omega slots, padded
     const int nqt = (K + 15) / 16;                               // q tiles of the omega GEMM
+    float4* XY = reinterpret_cast<float4*>(smem_raw);            // [nqt*16][ncw] X, Y parts
+    float2* A_s = reinterpret_cast<float2*>(XY + nqt * 16 * ncw);
+    float2* h_s = A_s + L * L;
+    float2* S_s = h_s + L * L;                                   // [K][K], stages 1-2
+    float* PMt = reinterpret_cast<float*>(S_s);                  // [4][KP][cstride], fold and
+                                                                 // stage 3 (S_s is dead by then)
+    float2* tw = S_s + max(KK, 2 * KP * cs_);                    // [n_phi] cos/sin(2 pi j/n_phi)
     float2* twW = tw + a.n_phi;                                  // [KP][ncw] cos/sin(k omega_cs)
-    float4* XY = reinterpret_cast<float4*>(twW + KP * ncw);      // [nqt*16][ncw] X, Y parts
+    float* D_s = reinterpret_cast<float*>(twW + KP * ncw);       // canonical d row of this block
     const int tid = threadIdx.x, nth = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
 
@@ -63,7 +67,10 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
     const int l = a.l_lo + lidx;
 
     for (int i = tid; i < a.n_phi; i += nth) tw[i] = a.twfull[i];
-    for (int i = tid; i < 4 * KP * cs_; i += nth) PMt[i] = 0.0f;
+    {
+        const float* drow = a.dtab + (int64_t)t * a.dstride;
+        for (int i = tid; i < a.dstride; i += nth) D_s[i] = drow[i];
+    }
     for (int i = tid; i < KP * ncw; i += nth) {
         const int k = i / ncw, cs = i - k * ncw;
         float2 v = vmk<float2>(0.0f, 0.0f);
@@ -79,7 +86,6 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
 #pragma unroll
         for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
 
-    const float* drow = a.dtab + (int64_t)t * a.dstride;
     const int nrep = ring_items(L);
     const int nm = a.real_pair ? l + 1 : 2 * l + 1;
     for (int mi = 0; mi < nm; ++mi) {
@@ -94,7 +100,7 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
             int s_, q, qp;
             ring_item(r, L, s_, q, qp);
             float2 v, vm;
-            theta_pair<float, float2, 8>(drow, A_s, h_s, L, s_, q, qp, v, vm);
+            theta_pair<float, float2, 4>(D_s, A_s, h_s, L, s_, q, qp, v, vm);
             S_s[(q + L - 1) * K + (qp + L - 1)] = v;
             if (s_ > 0) S_s[(L - 1 - q) * K + (L - 1 - qp)] = vm;
         }
@@ -109,7 +115,8 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
             const int kq2 = lane >> 4, c16 = lane & 15;
             const int qi = qt * 16 + c16;
             f4v xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0}, yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
-            for (int kk = 0; kk < KP / 4; ++kk) {
+#pragma unroll
+            for (int kk = 0; kk < NKK; ++kk) {
                 const int k = kk * 4 + kq2;
                 float2 ap = vmk<float2>(0.0f, 0.0f), am = vmk<float2>(0.0f, 0.0f);
                 if (qi < K && k < L) {
@@ -122,7 +129,7 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
                         am = vsub(s1, s2);
                     }
                 }
-                const float2 w = twW[k * ncw + ct2 * 16 + c16];
+                const float2 w = k < KP ? twW[k * ncw + ct2 * 16 + c16] : vmk<float2>(0.0f, 0.0f);
                 xr = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.x, w.x, xr, 0, 0, 0);
                 xi = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.y, w.x, xi, 0, 0, 0);
                 yr = __builtin_amdgcn_mfma_f32_16x16x4f32(am.x, w.y, yr, 0, 0, 0);
@@ -165,6 +172,12 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
                 PMt[(3 * KP + qa) * cs_ + c] = M.y;
             }
         }
+        // rows L..KP-1 of the B table are read as zeros by stage 3
+        for (int idx = tid; idx < 4 * (KP - L) * cs_; idx += nth) {
+            const int part = idx / ((KP - L) * cs_);
+            const int rem = idx - part * (KP - L) * cs_;
+            PMt[(part * KP + L) * cs_ + rem] = 0.0f;
+        }
         __syncthreads();
 
         // stage 3: MFMA phi synthesis and energy accumulation.  Wave w owns omega tile
@@ -177,11 +190,11 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
         const int kq = lane_o >> 4, col = lane_o & 15;
         const int nkk = KP / 4;
         const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
-        float breg[4][8];
+        float breg[4][NKK];
         {
             const int bcol = ct * 16 + col;
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
+            for (int kk = 0; kk < NKK; ++kk) {
                 const int k = kk * 4 + kq;
 #pragma unroll
                 for (int part = 0; part < 4; ++part)
@@ -197,17 +210,21 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
             while (step4 >= a.n_phi) step4 -= a.n_phi;
             int idx = kq * as;                                 // (kq as) mod n_phi, kq < 4
             while (idx >= a.n_phi) idx -= a.n_phi;
-            f4v cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0}, sre = {0, 0, 0, 0}, sim = {0, 0, 0, 0};
+            // A fragments of all k-steps first (k beyond L meets a zero B row)
+            float2 cz[NKK];
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                if (kk >= nkk) break;
-                const float2 cz = tw[idx];
-                cre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, breg[0][kk], cre, 0, 0, 0);
-                cim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.x, breg[1][kk], cim, 0, 0, 0);
-                sre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, breg[2][kk], sre, 0, 0, 0);
-                sim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz.y, breg[3][kk], sim, 0, 0, 0);
+            for (int kk = 0; kk < NKK; ++kk) {
+                cz[kk] = tw[idx];
                 idx += step4;
                 if (idx >= a.n_phi) idx -= a.n_phi;
+            }
+            f4v cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0}, sre = {0, 0, 0, 0}, sim = {0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < NKK; ++kk) {
+                cre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].x, breg[0][kk], cre, 0, 0, 0);
+                cim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].x, breg[1][kk], cim, 0, 0, 0);
+                sre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].y, breg[2][kk], sre, 0, 0, 0);
+                sim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].y, breg[3][kk], sim, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -255,9 +272,10 @@ static int energy_cstride(int nctp) {
 static size_t energy_lds_bytes(const DevPlan& P, int KP, int cstride) {
     const int L = P.d.L_h, K = 2 * L - 1;
     const int ncw = (P.d.n_omega / 2 + 1 + 15) / 16 * 16, nqt = (K + 15) / 16;
-    return (size_t)(2 * L * L + K * K) * sizeof(float2) + (size_t)4 * KP * cstride * sizeof(float) +
-           (size_t)P.d.n_phi * sizeof(float2) + (size_t)KP * ncw * sizeof(float2) +
-           (size_t)nqt * 16 * ncw * sizeof(float4);
+    const size_t sp = std::max((size_t)K * K, (size_t)2 * KP * cstride);   // S_s | PMt
+    return (size_t)nqt * 16 * ncw * sizeof(float4) + (size_t)2 * L * L * sizeof(float2) +
+           sp * sizeof(float2) + (size_t)P.d.n_phi * sizeof(float2) +
+           (size_t)KP * ncw * sizeof(float2) + (size_t)dtab_row_len(L) * sizeof(float);
 }
 
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
@@ -289,18 +307,21 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
     const size_t lds = energy_lds_bytes(P, a.KP, a.cstride);
     const int per = kEnergyWaves / a.nctp;           // waves sharing one omega tile
     const int tpw = (a.nst + per - 1) / per;
-    dim3 grid(a.nblk), block(64 * kEnergyWaves);
-    if (lds > 64 * 1024) {
-        const void* fns[] = {(const void*)energy_kernel<4>, (const void*)energy_kernel<8>,
-                             (const void*)energy_kernel<12>, (const void*)energy_kernel<17>};
-        for (const void* fn : fns)
-            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    }
-    if (tpw <= 4) hipLaunchKernelGGL(energy_kernel<4>, grid, block, lds, s, a);
-    else if (tpw <= 8) hipLaunchKernelGGL(energy_kernel<8>, grid, block, lds, s, a);
-    else if (tpw <= 12) hipLaunchKernelGGL(energy_kernel<12>, grid, block, lds, s, a);
-    else if (tpw <= 17) hipLaunchKernelGGL(energy_kernel<17>, grid, block, lds, s, a);
-    else return hipErrorInvalidValue;
+    const int nkk = a.KP / 4;
+    const int ki = nkk <= 2 ? 0 : (nkk <= 4 ? 1 : 2);
+    const int ti = tpw <= 4 ? 0 : (tpw <= 8 ? 1 : (tpw <= 12 ? 2 : (tpw <= 17 ? 3 : -1)));
+    if (ti < 0) return hipErrorInvalidValue;
+    const void* fns[4][3] = {
+        {(const void*)energy_kernel<4, 2>, (const void*)energy_kernel<4, 4>, (const void*)energy_kernel<4, 8>},
+        {(const void*)energy_kernel<8, 2>, (const void*)energy_kernel<8, 4>, (const void*)energy_kernel<8, 8>},
+        {(const void*)energy_kernel<12, 2>, (const void*)energy_kernel<12, 4>, (const void*)energy_kernel<12, 8>},
+        {(const void*)energy_kernel<17, 2>, (const void*)energy_kernel<17, 4>, (const void*)energy_kernel<17, 8>}};
+    const void* fn = fns[ti][ki];
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    void* args[] = {&a};
+    const hipError_t e = hipLaunchKernel(fn, dim3(a.nblk), dim3(64 * kEnergyWaves), args, lds, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

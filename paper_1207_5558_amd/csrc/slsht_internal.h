@@ -1,5 +1,6 @@
 // Internal interface between the host core (slsht_api.cpp, slsht_server.cpp)
-// and the gfx950 kernels (slsht_kernels.hip).  Not part of the public ABI.
+// and the gfx950 kernels (slsht_kernels.hip, slsht_synth.hip, slsht_energy.hip).  Not part
+// of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,11 +14,13 @@
 
 namespace slsht {
 
-// Number of Wigner-d entries d^p_{q,q'} with p < L, |q|,|q'| <= p:
-// sum_{p<L} (2p+1)^2 = L(4L^2-1)/3.
-inline int64_t dtab_row_len(int L) { return (int64_t)L * (4LL * L * L - 1) / 3; }
+// Wigner-d table rows hold the canonical entries d^p_{Q,Q'}(theta_b), p < L,
+// 0 <= Q <= p, -Q <= Q' <= Q, at dtab_off(p) + Q^2 + Q + Q'; every other (q, q')
+// follows from d_{q,q'} = (-1)^{q-q'} d_{q',q} = d_{-q',-q} (Section IV-B).
+// Entries per row: sum_{p<L} (p+1)^2 = L(L+1)(2L+1)/6, a quarter of the full set.
+inline int64_t dtab_row_len(int L) { return (int64_t)L * (L + 1) * (2 * L + 1) / 6; }
 // Offset of degree p inside one theta row of the table.
-__host__ __device__ inline int dtab_off(int p) { return p * (4 * p * p - 1) / 3; }
+__host__ __device__ inline int dtab_off(int p) { return p * (p + 1) * (2 * p + 1) / 6; }
 
 // Device tables shared by every descriptor with the same window band-limit, grid,
 // theta rows, precision and output kind: Wigner-d(theta_b), phi/omega twiddles,
@@ -26,7 +29,7 @@ struct Tables {
     int device = 0;
     int L_h = 0, n_phi = 0, n_theta = 0, n_omega = 0, theta_lo = 0, theta_hi = 0, precision = 0;
     bool energy = false;
-    void* dtab = nullptr;       // [n_theta_out][dtab_row_len(L_h)] double or float
+    void* dtab = nullptr;       // [n_theta_out][dtab_row_len(L_h)] double or float, canonical
     void* tw_phi = nullptr;     // [L_h-1][(n_phi+1)/2] (cos, sin) double2 or float2
     void* tw_omega = nullptr;   // [L_h-1][n_omega/2+1] (cos, sin) double2 or float2
     void* tw_full = nullptr;    // ENERGY: [n_phi] float2 (cos, sin)(2 pi j / n_phi)

@@ -24,13 +24,13 @@
 namespace slsht {
 
 // ------------------------------------------------------------------------------
-// K1: Wigner-d table.  One thread per (theta row, q, q'); the thread seeds
+// K1: Wigner-d table.  One thread per (theta row, canonical pair Q >= |Q'|); the thread seeds
 // d^{p0}_{q,q'} at p0 = max(|q|,|q'|) from the one-term form of Wigner's sum
 // and climbs in p with the three-term recursion
 //   p sqrt(((p+1)^2-q^2)((p+1)^2-q'^2)) d^{p+1}
 //     = (2p+1)(p(p+1) cos(beta) - q q') d^p - (p+1) sqrt((p^2-q^2)(p^2-q'^2)) d^{p-1},
-// all in FP64; consecutive threads hold consecutive q', so each degree's row
-// segment is written contiguously.  beta = 2 pi b / n_phi (grid E_L, Section II-D).
+// all in FP64; consecutive threads hold consecutive canonical pairs, so each degree's
+// row segment is written contiguously.  beta = 2 pi b / n_phi (grid E_L, Section II-D).
 
 __device__ __forceinline__ double ipow(double x, int n) {
     double r = 1.0;
@@ -41,12 +41,13 @@ __device__ __forceinline__ double ipow(double x, int n) {
 template <typename OutT>
 __global__ void wigner_table_kernel(OutT* __restrict__ tab, int L, int n_phi, int theta_lo,
                                     int n_rows, int64_t row_len) {
-    const int K = 2 * L - 1;
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pair = blockIdx.x * blockDim.x + threadIdx.x;   // = q^2 + q + q'
     const int row = blockIdx.y;
-    if (pair >= K * K || row >= n_rows) return;
-    const int q = pair / K - (L - 1);
-    const int qp = pair % K - (L - 1);
+    if (pair >= L * L || row >= n_rows) return;
+    int q = (int)sqrtf((float)pair);
+    while (q * q > pair) --q;
+    while ((q + 1) * (q + 1) <= pair) ++q;
+    const int qp = pair - q * q - q;
     const int b = theta_lo + row;
     double sh, ch;                       // sin(beta/2), cos(beta/2), beta/2 = pi b / n_phi
     sincospi((double)b / (double)n_phi, &sh, &ch);
@@ -70,7 +71,7 @@ __global__ void wigner_table_kernel(OutT* __restrict__ tab, int L, int n_phi, in
     double dprev = 0.0;
     const double qq = (double)q * (double)qp;
     for (int p = j0; p < L; ++p) {
-        out[dtab_off(p) + (q + p) * (2 * p + 1) + (qp + p)] = (OutT)d;
+        out[dtab_off(p) + pair] = (OutT)d;
         if (p + 1 >= L) break;
         double dn;
         if (p == 0) {
@@ -87,8 +88,8 @@ __global__ void wigner_table_kernel(OutT* __restrict__ tab, int L, int n_phi, in
 }
 
 hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s) {
-    const int L = P.d.L_h, K = 2 * L - 1;
-    dim3 block(128), grid((K * K + 127) / 128, P.n_theta_out);
+    const int L = P.d.L_h;
+    dim3 block(128), grid((L * L + 127) / 128, P.n_theta_out);
     const int64_t rl = dtab_row_len(L);
     if (P.d.precision == SLSHT_FP64)
         hipLaunchKernelGGL(wigner_table_kernel<double>, grid, block, 0, s, (double*)P.T->dtab, L,

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
         int s_, q, qp;
         ring_item(idx - t * nrep, L, s_, q, qp);
         V v, vm;
-        theta_pair<T, V, (LH < 16 ? LH : 16)>(dt + (int64_t)(t0 + t) * a.dstride, A_s, h_s, L, s_, q, qp, v, vm);
+        theta_pair<T, V, (sizeof(T) == 8 ? 4 : 8)>(dt + (int64_t)(t0 + t) * a.dstride, A_s, h_s, L, s_, q, qp, v, vm);
         S_s[t * KK + (q + L - 1) * K + (qp + L - 1)] = v;
         if (s_ > 0) S_s[t * KK + (L - 1 - q) * K + (L - 1 - qp)] = vm;
     }

@@ -78,8 +78,9 @@ def test_footprints_match_layouts(lib):
     wl5 = workload("large")
     n_l = wl5.l_hi - wl5.l_lo
     assert api.footprint(api.desc_for(wl5))[1] == n_l * wl5.n_rho * 4   # float energy
-    # the plan holds the d table (136 rows x 680 entries of FP64) plus small tables
-    assert plan_b >= 136 * 680 * 8
+    # the plan holds the canonical d table (136 rows x 204 entries of FP64: p < 8,
+    # 0 <= Q <= p, |Q'| <= Q) plus small tables
+    assert plan_b >= 136 * 204 * 8
     assert scr == 0
     d = _desc(theta_lo=2, theta_hi=5)
     assert api.footprint(d)[1] == 64 * 5 * 3 * 21 * 16
