@@ -158,6 +158,31 @@ def energy_leg(torch, api, steps):
     return out
 
 
+def steerable_leg(torch, api, steps, warmup):
+    """The mid-size workload with a steerable window (azimuthal band-limit 3): the theta
+    and omega contractions run over |q'| < 3 and 5 omega samples carry all of g."""
+    from paper_1207_5558_amd.inputs import make_inputs, workload
+    wl = workload("mid_steer")
+    f, h = make_inputs(wl)
+    ft, ht = torch.from_numpy(f).to("cuda:0"), torch.from_numpy(h).to("cuda:0")
+    plan = api.Plan(api.desc_for(wl), device=0)
+    g = plan.empty_output()
+    _, per, cpl = time_forward(plan, ft, ht, g, steps, warmup, torch, api)
+    ms, kern = float(per.mean()), float(per.mean() - cpl.mean())
+    L = wl.L_h
+    out_b = g.numel() * g.element_size()
+    alg = out_b + wl.n_lm * L * L * 16 + L * L * 16 + wl.n_theta * (L * (L + 1) * (2 * L + 1) // 6) * 8
+    log(f"steerable mid: forward {ms:.3f} ms, {wl.samples / (ms * 1e-3):.3e} samples/s")
+    del g, plan
+    torch.cuda.empty_cache()
+    return {"workload": "mid_steer: L_f=128, L_h=8, azimuthal band-limit 3, l in [32,48) all m, "
+                        "271 x 136 x 5 grid, FP64", "ms_per_step": ms,
+            "value": wl.samples / (ms * 1e-3), "unit": "samples/s",
+            "roofline": {"bound": "hbm", "achieved": alg / (kern * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / (kern * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
 def serving_leg(n, rate):
     """Continuous batching of the serving workload: n requests with Poisson arrivals at
     `rate` req/s, L_f in {32..192}, L_h in {4,8,16}, width-8 l-windows, half FP64 and half
@@ -204,6 +229,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-n", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, req/s")
+    ap.add_argument("--serve-rate-sat", type=float, default=20000.0,
+                    help="arrival rate of the second, saturating serving run (capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -298,12 +325,17 @@ def main():
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": alg32 / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
+    line["steerable_mid"] = steerable_leg(torch, api, args.steps, args.warmup)
+
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM
     if not args.no_energy:
         line["energy_large"] = energy_leg(torch, api, args.steps_energy)
     if not args.no_serve:
         line["serving"] = serving_leg(args.serve_n, args.serve_rate)
+        sat = serving_leg(args.serve_n, args.serve_rate_sat)
+        line["serving"]["saturated"] = {k: sat[k] for k in ("arrival_rate_hz", "value", "unit",
+                                                            "span_s", "p50_ms", "p99_ms")}
 
     if not args.no_cpu:
         log("CPU baseline: oracle on a sample of rotations")

@@ -89,6 +89,12 @@ typedef struct {
     uint32_t flags;       /* 0 or SLSHT_REAL_PAIR                                   */
     int32_t theta_lo;     /* first theta row computed, 0 <= theta_lo < theta_hi     */
     int32_t theta_hi;     /* one past the last row; 0 means n_theta                 */
+    int32_t n_az;         /* azimuthal band-limit of a steerable window: h_s^r = 0  */
+                          /* for |r| >= n_az (such coefficients are not read);      */
+                          /* 0 <= n_az <= L_h, 0 means L_h (Section IV-B, remark on */
+                          /* steerable windows).  The theta and omega contractions  */
+                          /* then run over |q'| < n_az only, and n_omega = 2 n_az-1 */
+                          /* samples of omega determine g for every omega.          */
 } slsht_desc;
 
 typedef struct slsht_plan_s* slsht_plan_t;
@@ -153,8 +159,9 @@ int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream);
  *   g: device, FULL layout of this plan;  h: device complex128[L_h * L_h] (only
  *   h_0^0 is read, on the host, with a synchronous 16-byte copy);
  *   f_out: device complex128[l_hi^2 - l_lo^2].
- * Requires a FULL plan over all theta rows with n_phi, n_omega >= 2 L_h - 1,
- * and h_0^0 != 0 (SLSHT_EINVAL otherwise).  Asynchronous after the h_0^0 read. */
+ * Requires a FULL plan over all theta rows with n_phi >= 2 L_h - 1,
+ * n_omega >= 2 n_az - 1 (n_az = L_h unless the window is steerable), and
+ * h_0^0 != 0 (SLSHT_EINVAL otherwise).  Asynchronous after the h_0^0 read. */
 int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream);
 
 /* ---------------------------------------------------------------------------

@@ -29,7 +29,8 @@ class Desc(ctypes.Structure):
                 ("n_phi", ctypes.c_int32), ("n_theta", ctypes.c_int32),
                 ("n_omega", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("output_mode", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("theta_lo", ctypes.c_int32), ("theta_hi", ctypes.c_int32)]
+                ("theta_lo", ctypes.c_int32), ("theta_hi", ctypes.c_int32),
+                ("n_az", ctypes.c_int32)]
 
 
 class SlshtError(RuntimeError):

@@ -17,14 +17,15 @@ _MODE = {"full": L.SLSHT_OUT_FULL, "energy": L.SLSHT_OUT_ENERGY}
 
 
 def make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, precision="fp64", output="full",
-              real_pair=False, theta_lo=0, theta_hi=0) -> L.Desc:
+              real_pair=False, theta_lo=0, theta_hi=0, n_az=0) -> L.Desc:
     return L.Desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, _PREC[precision],
-                  _MODE[output], L.SLSHT_REAL_PAIR if real_pair else 0, theta_lo, theta_hi)
+                  _MODE[output], L.SLSHT_REAL_PAIR if real_pair else 0, theta_lo, theta_hi,
+                  n_az)
 
 
 def desc_for(wl, **over) -> L.Desc:
     """Descriptor of a workload from paper_1207_5558_amd.inputs."""
-    kw = dict(precision=wl.precision, output=wl.output)
+    kw = dict(precision=wl.precision, output=wl.output, n_az=wl.n_az)
     kw.update(over)
     return make_desc(wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta, wl.n_omega, **kw)
 

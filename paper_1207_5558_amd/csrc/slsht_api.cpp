@@ -147,6 +147,8 @@ int check_desc(const slsht_desc* d) {
         return set_error(SLSHT_EINVAL, "unknown output_mode %d", d->output_mode);
     if (d->flags & ~(uint32_t)SLSHT_REAL_PAIR)
         return set_error(SLSHT_EINVAL, "unknown flags 0x%x", d->flags);
+    if (d->n_az < 0 || d->n_az > d->L_h)
+        return set_error(SLSHT_EINVAL, "n_az=%d outside [0, L_h=%d]", d->n_az, d->L_h);
     const int thi = theta_hi_of(*d);
     if (d->theta_lo < 0 || thi <= d->theta_lo || thi > d->n_theta)
         return set_error(SLSHT_EINVAL, "need 0 <= theta_lo < theta_hi <= n_theta (got %d, %d)",
@@ -414,8 +416,9 @@ int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, 
     if (P.d.theta_lo != 0 || P.d.theta_hi != P.d.n_theta)
         return slsht::set_error(SLSHT_EINVAL,
                                 "inverse needs every theta row (theta_lo=0, theta_hi=n_theta)");
-    if (P.d.n_phi < 2 * P.d.L_h - 1 || P.d.n_omega < 2 * P.d.L_h - 1)
-        return slsht::set_error(SLSHT_EINVAL, "inverse needs n_phi, n_omega >= 2 L_h - 1");
+    if (P.d.n_phi < 2 * P.d.L_h - 1 || P.d.n_omega < 2 * slsht::n_az_of(P.d) - 1)
+        return slsht::set_error(SLSHT_EINVAL,
+                                "inverse needs n_phi >= 2 L_h - 1 and n_omega >= 2 n_az - 1");
     DeviceGuard guard(plan->device);
     if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;

@@ -62,6 +62,31 @@ __device__ __forceinline__ void ring_item(int r, int L, int& s, int& q, int& qp)
     else { qp = s; q = -s + (j - 2 * s); }
 }
 
+// Theta-stage items for a window with azimuthal band-limit N (S_{q,q'} = 0 for
+// |q'| >= N, so only |q'| < N is computed).  N = L: the ring order above.  N < L
+// (steerable window): q' = 0 with q = 0..L-1 first, then q' = 1..N-1 with every q; each
+// item again covers (q, q') and (-q, -q').
+__device__ __forceinline__ int theta_items(int L, int N) {
+    return N >= L ? ring_items(L) : L + (N - 1) * (2 * L - 1);
+}
+
+__device__ __forceinline__ void theta_item(int r, int L, int N, int& s, int& q, int& qp) {
+    if (N >= L) {
+        ring_item(r, L, s, q, qp);
+        return;
+    }
+    if (r < L) {
+        q = r;
+        qp = 0;
+    } else {
+        const int K = 2 * L - 1, x = r - L;
+        qp = 1 + x / K;
+        q = x - (qp - 1) * K - (L - 1);
+    }
+    const int aq = q < 0 ? -q : q;
+    s = aq > qp ? aq : qp;
+}
+
 // Canonical table entry of d^p_{q,q'}: d_{q,q'} = sign * d_{Q,Q'} with Q = max(|q|,|q'|)
 // >= |Q'|, from d_{q,q'} = (-1)^{q-q'} d_{q',q} = d_{-q',-q} (symmetries of Section IV-B).
 __device__ __forceinline__ void d_canonical(int q, int qp, int& Q, int& Qp, bool& neg) {

@@ -34,6 +34,7 @@ struct EnergyArgs {
     int64_t dstride;
     int L, K, KP, l_lo, n_l, n_phi, n_omega, n_theta_out, nslot, ncp, nst, nct, nctp, cstride;
     int real_pair, nblk;
+    int N;        // azimuthal band-limit of the window (|q'| < N)
 };
 
 constexpr int kEnergyWaves = 8;
@@ -86,19 +87,21 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
 #pragma unroll
         for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
 
-    const int nrep = ring_items(L);
+    const int nrep = theta_items(L, a.N);
     const int nm = a.real_pair ? l + 1 : 2 * l + 1;
     for (int mi = 0; mi < nm; ++mi) {
         const int m = a.real_pair ? mi : mi - l;
-        const float wgt = (a.real_pair && m > 0) ? 2.0f : 1.0f;
+        // real pair: E = 2 (|g_0|^2 / 2 + sum_{m>0} |g_m|^2); the m = 0 half-weight is
+        // applied by scaling that order's B fragments by sqrt(1/2), the factor 2 at the store
+        const float bscale = (a.real_pair && m == 0) ? 0.70710678118654752f : 1.0f;
         const int64_t lm = (int64_t)l * l + l + m - (int64_t)a.l_lo * a.l_lo;
         for (int i = tid; i < L * L; i += nth) A_s[i] = vcast<float2>(a.A[lm * L * L + i]);
         __syncthreads();
 
-        // stage 1: theta contraction, ring-ordered items (see ring_item / theta_pair)
+        // stage 1: theta contraction over |q'| < N (see theta_item / theta_pair)
         for (int r = tid; r < nrep; r += nth) {
             int s_, q, qp;
-            ring_item(r, L, s_, q, qp);
+            theta_item(r, L, a.N, s_, q, qp);
             float2 v, vm;
             theta_pair<float, float2, 4>(D_s, A_s, h_s, L, s_, q, qp, v, vm);
             S_s[(q + L - 1) * K + (qp + L - 1)] = v;
@@ -119,7 +122,7 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
             for (int kk = 0; kk < NKK; ++kk) {
                 const int k = kk * 4 + kq2;
                 float2 ap = vmk<float2>(0.0f, 0.0f), am = vmk<float2>(0.0f, 0.0f);
-                if (qi < K && k < L) {
+                if (qi < K && k < a.N) {
                     const float2* row = S_s + qi * K + (L - 1);
                     if (k == 0) {
                         ap = row[0];
@@ -198,7 +201,7 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
                 const int k = kk * 4 + kq;
 #pragma unroll
                 for (int part = 0; part < 4; ++part)
-                    breg[part][kk] = kk < nkk ? PMt[(part * KP + k) * cs_ + bcol] : 0.0f;
+                    breg[part][kk] = kk < nkk ? bscale * PMt[(part * KP + k) * cs_ + bcol] : 0.0f;
             }
         }
 #pragma unroll
@@ -230,8 +233,8 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
             for (int r = 0; r < 4; ++r) {
                 const float pr = cre[r] + sre[r], pi = cim[r] + sim[r];
                 const float mr = cre[r] - sre[r], mi2 = cim[r] - sim[r];
-                Ep[j][r] += wgt * (pr * pr + pi * pi);
-                Em[j][r] += wgt * (mr * mr + mi2 * mi2);
+                Ep[j][r] = fmaf(pi, pi, fmaf(pr, pr, Ep[j][r]));
+                Em[j][r] = fmaf(mi2, mi2, fmaf(mr, mr, Em[j][r]));
             }
             // Materialise this tile's energy here, so that its four MFMA accumulators die
             // before the next tile starts (otherwise the updates sink to the end of the
@@ -243,6 +246,7 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
     }
 
     // store: lane holds slots st*16 + 4*(lane/16) + r of omega column ct*16 + lane%16
+    const float escale = a.real_pair ? 2.0f : 1.0f;
     const int kq = lane >> 4, col = lane & 15;
     const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
 #pragma unroll
@@ -256,8 +260,8 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
         for (int r = 0; r < 4; ++r) {
             const int s = st * 16 + 4 * kq + r;
             if (s >= a.nslot) continue;
-            row[s] = Ep[j][r];
-            if (s > 0) row[a.n_phi - s] = Em[j][r];
+            row[s] = escale * Ep[j][r];
+            if (s > 0) row[a.n_phi - s] = escale * Em[j][r];
         }
     }
 }
@@ -304,6 +308,7 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
     a.cstride = energy_cstride(a.nctp);
     a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     a.nblk = a.n_l * P.n_theta_out;
+    a.N = n_az_of(P.d);
     const size_t lds = energy_lds_bytes(P, a.KP, a.cstride);
     const int per = kEnergyWaves / a.nctp;           // waves sharing one omega tile
     const int tpw = (a.nst + per - 1) / per;

@@ -22,6 +22,9 @@ inline int64_t dtab_row_len(int L) { return (int64_t)L * (L + 1) * (2 * L + 1) /
 // Offset of degree p inside one theta row of the table.
 __host__ __device__ inline int dtab_off(int p) { return p * (p + 1) * (2 * p + 1) / 6; }
 
+// Azimuthal band-limit of the window: h_s^r = 0 for |r| >= n_az (n_az = L_h if unset).
+inline int n_az_of(const slsht_desc& d) { return d.n_az > 0 ? d.n_az : d.L_h; }
+
 // Device tables shared by every descriptor with the same window band-limit, grid,
 // theta rows, precision and output kind: Wigner-d(theta_b), phi/omega twiddles,
 // beta weights.  Freed when the last plan using them goes away.

@@ -39,6 +39,7 @@ struct SynthArgs {
     void* g;
     int64_t dstride;
     int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp, l_lo, real_pair;
+    int N;        // azimuthal band-limit of the window (|q'| < N)
     int xsize;    // elements of the A/h | P/M union region in LDS
 };
 
@@ -185,14 +186,14 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     for (int i = tid; i < (L - 1) * a.ncp; i += nth) TW_s[i] = twg[i];
     __syncthreads();
 
-    // stage 1: theta contraction, ring-ordered items (see ring_item / theta_pair)
+    // stage 1: theta contraction over |q'| < N (see theta_item / theta_pair)
     const T* dt = reinterpret_cast<const T*>(a.dtab);
     const int KK = K * K;
-    const int nrep = ring_items(L);
+    const int nrep = theta_items(L, a.N);
     for (int idx = tid; idx < tb * nrep; idx += nth) {
         const int t = idx / nrep;
         int s_, q, qp;
-        ring_item(idx - t * nrep, L, s_, q, qp);
+        theta_item(idx - t * nrep, L, a.N, s_, q, qp);
         V v, vm;
         theta_pair<T, V, (sizeof(T) == 8 ? 4 : 8)>(dt + (int64_t)(t0 + t) * a.dstride, A_s, h_s, L, s_, q, qp, v, vm);
         S_s[t * KK + (q + L - 1) * K + (qp + L - 1)] = v;
@@ -212,7 +213,7 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
         const V* Sm = S_s + t * KK + (L - 1 - qa) * K;
         V Xp = Sp[L - 1], Xm = Sm[L - 1];
         V Yp = vmk<V>(0, 0), Ym = vmk<V>(0, 0);
-        for (int k = 1; k < L; ++k) {
+        for (int k = 1; k < a.N; ++k) {
             const V tw = twom[(k - 1) * a.ncp + cs];
             const V a1 = Sp[L - 1 + k], a2 = Sp[L - 1 - k];
             const V b1 = Sm[L - 1 + k], b2 = Sm[L - 1 - k];
@@ -513,6 +514,7 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
     a.l_lo = P.d.l_lo;
     a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     a.xsize = (int)synth_xsize(P, P.tb);
+    a.N = n_az_of(P.d);
     const int64_t nblk = (int64_t)P.n_items * a.n_tiles;
     void* args[] = {&a};
     return hipLaunchKernel(synth_fn(P), dim3((unsigned)nblk), dim3(P.block), args, P.lds_bytes, s);

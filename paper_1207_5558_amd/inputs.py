@@ -34,9 +34,10 @@ __all__ = [
 ]
 
 
-def grid_dims(L_f: int, L_h: int) -> tuple[int, int, int]:
-    """(n_phi, n_theta, n_omega) of the oversampled SO(3) grid used by all workloads."""
-    return 2 * (L_f + L_h) - 1, L_f + L_h, 2 * L_h - 1
+def grid_dims(L_f: int, L_h: int, n_az: int = 0) -> tuple[int, int, int]:
+    """(n_phi, n_theta, n_omega) of the oversampled SO(3) grid used by all workloads;
+    a steerable window (azimuthal band-limit n_az < L_h) needs 2 n_az - 1 omega samples."""
+    return 2 * (L_f + L_h) - 1, L_f + L_h, 2 * (n_az or L_h) - 1
 
 
 def n_lm(l_lo: int, l_hi: int) -> int:
@@ -59,6 +60,7 @@ class Workload:
     zero_dc: bool        # f_0^0 = 0
     precision: str       # "fp64" or "fp32"
     output: str          # "full" or "energy"
+    n_az: int = 0        # azimuthal band-limit of a steerable window (0: L_h)
 
     @property
     def n_lm(self) -> int:
@@ -73,10 +75,10 @@ class Workload:
         return self.n_lm * self.n_rho
 
 
-def _wl(name, L_f, L_h, l_lo, l_hi, seed, spectrum, zero_dc, precision, output):
-    n_phi, n_theta, n_omega = grid_dims(L_f, L_h)
+def _wl(name, L_f, L_h, l_lo, l_hi, seed, spectrum, zero_dc, precision, output, n_az=0):
+    n_phi, n_theta, n_omega = grid_dims(L_f, L_h, n_az)
     return Workload(name, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, seed,
-                    spectrum, zero_dc, precision, output)
+                    spectrum, zero_dc, precision, output, n_az)
 
 
 WORKLOADS = {
@@ -89,6 +91,9 @@ WORKLOADS = {
     # topography-like map: L_f=512, L_h=32, l in [100,116), 1087x544x63 grid,
     # l^-2.5 spectrum, FP32-mixed, output reduced to sum_m |g|^2 per (l, rho)
     "large": _wl("large", 512, 32, 100, 116, 4, 2.5, True, "fp32", "energy"),
+    # "mid" with a steerable window: azimuthal band-limit 3 (h_s^r = 0 for |r| >= 3),
+    # so omega needs 2*3-1 = 5 samples: 271x136x5 grid, FP64
+    "mid_steer": _wl("mid_steer", 128, 8, 32, 48, 1, 2.0, True, "fp64", "full", n_az=3),
 }
 
 
@@ -124,14 +129,21 @@ def draw_coefficients(rng: np.random.Generator, L: int, spectrum: float = 0.0,
     return out
 
 
-def draw_window(rng: np.random.Generator, L_h: int, min_dc: float = 1e-3) -> np.ndarray:
+def draw_window(rng: np.random.Generator, L_h: int, min_dc: float = 1e-3,
+                n_az: int = 0) -> np.ndarray:
     """Random asymmetric band-limited window, real-signal consistent, unit energy.
 
-    Redrawn (from the same generator) while |h_0^0| < min_dc, because the
-    inverse transform divides by h_0^0.
+    With n_az > 0 the window is steerable: h_s^r is set to zero for |r| >= n_az after
+    the draw (the draw itself is unchanged).  Redrawn (from the same generator) while
+    |h_0^0| < min_dc, because the inverse transform divides by h_0^0.
     """
     while True:
         h = draw_coefficients(rng, L_h, 0.0, False)
+        if n_az:
+            for s in range(L_h):
+                for r in range(-s, s + 1):
+                    if abs(r) >= n_az:
+                        h[s * s + s + r] = 0.0
         h /= math.sqrt(float(np.sum(np.abs(h) ** 2)))
         if abs(h[0]) >= min_dc:
             return h
@@ -141,7 +153,7 @@ def make_inputs(wl: Workload) -> tuple[np.ndarray, np.ndarray]:
     """(f, h) for a workload; f first, then h, from default_rng(seed)."""
     rng = np.random.default_rng(wl.seed)
     f = draw_coefficients(rng, wl.L_f, wl.spectrum, wl.zero_dc)
-    h = draw_window(rng, wl.L_h)
+    h = draw_window(rng, wl.L_h, n_az=wl.n_az)
     return f, h
 
 

@@ -86,6 +86,15 @@ def test_footprints_match_layouts(lib):
     assert api.footprint(d)[1] == 64 * 5 * 3 * 21 * 16
 
 
+def test_steerable_window_rules(lib):
+    """n_az (azimuthal band-limit of the window) must lie in [0, L_h]."""
+    for az, ok in ((0, True), (1, True), (3, True), (-1, False), (4, False)):
+        d = _desc()
+        d.n_az = az
+        assert (lib.slsht_validate(ctypes.byref(d)) == L.SLSHT_OK) == ok, az
+    assert ctypes.sizeof(L.Desc) == 13 * 4
+
+
 def test_coupling_size(lib):
     d = api.desc_for(workload("mid"))
     assert lib.slsht_coupling_size(ctypes.byref(d)) == 1280 * 64
