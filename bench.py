@@ -183,6 +183,38 @@ def steerable_leg(torch, api, steps, warmup):
                          "frac": alg / (kern * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
+def windows_leg(torch, api, f_t, g_single, steps, warmup, n_windows=4):
+    """One signal of the mid-size workload against 4 windows (FP64): one coupling, four
+    syntheses (slsht_forward_windows)."""
+    from paper_1207_5558_amd.inputs import draw_window, workload
+    wl = workload("mid")
+    rng = np.random.default_rng(2)
+    hs = np.stack([draw_window(rng, wl.L_h) for _ in range(n_windows)])
+    ht = torch.from_numpy(hs).to("cuda:0")
+    plan = api.Plan(api.desc_for(wl), device=0)
+    g = torch.empty((n_windows,) + tuple(plan.output_shape), dtype=plan.output_dtype,
+                    device="cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.forward_windows(f_t, ht, g, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for s_, e_ in ev:
+        s_.record(stream)
+        plan.forward_windows(f_t, ht, g, stream=stream)
+        e_.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([s_.elapsed_time(e_) for s_, e_ in ev]))
+    log(f"{n_windows} windows, mid FP64: {ms:.3f} ms, "
+        f"{n_windows * wl.samples / (ms * 1e-3):.3e} samples/s")
+    del g, plan
+    torch.cuda.empty_cache()
+    return {"workload": f"mid FP64, one signal against {n_windows} windows (one coupling)",
+            "windows": n_windows, "ms_per_step": ms,
+            "value": n_windows * wl.samples / (ms * 1e-3), "unit": "samples/s"}
+
+
 def serving_leg(n, rate):
     """Continuous batching of the serving workload: n requests with Poisson arrivals at
     `rate` req/s, L_f in {32..192}, L_h in {4,8,16}, width-8 l-windows, half FP64 and half
@@ -326,6 +358,7 @@ def main():
                                        "frac": alg32 / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
     line["steerable_mid"] = steerable_leg(torch, api, args.steps, args.warmup)
+    line["windows_mid"] = windows_leg(torch, api, f_t, outputs["fp64"], args.steps, args.warmup)
 
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM

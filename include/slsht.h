@@ -151,6 +151,17 @@ int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void
  * windows, Section IV-B).  Asynchronous on `stream`. */
 int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream);
 
+/* Forward transform of one signal against several windows (remark on multiple
+ * windows, Section IV-B): the coupling of f is computed once and shared; each
+ * window then costs one synthesis.  Same plan rules as slsht_forward.
+ *   f: device, complex128[L_f * L_f]
+ *   h: device, complex128[n_windows][L_h * L_h]
+ *   g: device, n_windows consecutive outputs of slsht_forward's layout, each
+ *      out_bytes of slsht_footprint() long
+ * n_windows >= 1 (SLSHT_EINVAL otherwise).  Asynchronous on `stream`. */
+int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n_windows,
+                          void* g, void* stream);
+
 /* Inverse through the spectral marginal (Section III-C): for every (l, m) of the
  * plan,  f_hat = (1/(n_phi^2 n_omega)) sum_{a,b,c} q(theta_b) g(phi_a, theta_b, omega_c; l, m)
  * (eq. Eq:sig_reconstruction_discrete with per-axis sizes), and

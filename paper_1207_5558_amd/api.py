@@ -127,6 +127,25 @@ class Plan:
                                        _stream_handle(stream)))
         return A
 
+    def forward_windows(self, f: torch.Tensor, h: torch.Tensor, g: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+        """One signal against W windows h[W, L_h^2]; returns g[W, *output_shape]."""
+        d = self.desc
+        if h.dim() != 2 or h.shape[1] != d.L_h * d.L_h:
+            raise ValueError("h must be [n_windows, L_h^2]")
+        W = h.shape[0]
+        if g is None:
+            g = torch.empty((W,) + tuple(self.output_shape), dtype=self.output_dtype,
+                            device=f"cuda:{self.device}")
+        n_out = W
+        for s in self.output_shape:
+            n_out *= s
+        L.check(L.lib().slsht_forward_windows(
+            self._h, _dev_ptr(f, torch.complex128, d.L_f * d.L_f, "f"),
+            _dev_ptr(h, torch.complex128, W * d.L_h * d.L_h, "h"), W,
+            _dev_ptr(g, self.output_dtype, n_out, "g"), _stream_handle(stream)))
+        return g
+
     def inverse(self, g: torch.Tensor, h: torch.Tensor, f_out: torch.Tensor | None = None,
                 stream=None) -> torch.Tensor:
         d = self.desc

@@ -408,6 +408,28 @@ int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void
     return SLSHT_OK;
 }
 
+int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n_windows,
+                          void* g, void* stream) {
+    if (!plan || !f || !h || !g) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
+    if (n_windows < 1) return slsht::set_error(SLSHT_EINVAL, "n_windows=%d < 1", n_windows);
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    const slsht::DevPlan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = slsht::launch_coupling(P, (const double2*)f, P.A, s);
+    if (e != hipSuccess) return hip_fail(e, "coupling launch");
+    const size_t hn = (size_t)P.d.L_h * P.d.L_h;
+    const size_t ob = slsht::output_bytes(P.d);
+    for (int w = 0; w < n_windows; ++w) {
+        const double2* hw = (const double2*)h + w * hn;
+        void* gw = (char*)g + w * ob;
+        e = P.d.output_mode == SLSHT_OUT_FULL ? slsht::launch_synthesis(P, P.A, hw, gw, s)
+                                              : slsht::launch_energy(P, P.A, hw, (float*)gw, s);
+        if (e != hipSuccess) return hip_fail(e, "synthesis launch");
+    }
+    return SLSHT_OK;
+}
+
 int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream) {
     if (!plan || !g || !h || !f_out) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
     const slsht::DevPlan& P = plan->P;
