@@ -96,3 +96,23 @@ def test_inverse_normalisation_is_caught(monkeypatch):
     monkeypatch.setattr(osl, "oracle_marginal",
                         lambda g, a, b, c: orig(g, a, b, c) * a / (a + 1))
     _fails(pins.test_inverse_recovers_signal)
+
+
+def test_slepian_arc_integral_without_parity_factor_is_caught(monkeypatch):
+    import oracle.slepian as osl_ep
+    import tests.test_oracle_slepian as sl_pins
+    monkeypatch.setattr(osl_ep, "_arc_integral",
+                        lambda k, p: 4.0 * p if k == 0 else 4.0 * np.sin(k * p) / k)
+    _fails(sl_pins.test_ellipse_matrix_against_brute_force_indicator)
+
+
+def test_slepian_cap_without_sin_theta_weight_is_caught(monkeypatch):
+    import oracle.slepian as osl_ep
+    import tests.test_oracle_slepian as sl_pins
+    orig = osl_ep._theta_nodes
+
+    def bad(theta_c, a, n_cap, n_ts):
+        th1, w1, th2, w2, phs = orig(theta_c, a, n_cap, n_ts)
+        return th1, w1 / np.sqrt(1.0 - np.cos(th1) ** 2 + 1e-300), th2, w2, phs
+    monkeypatch.setattr(osl_ep, "_theta_nodes", bad)
+    _fails(sl_pins.test_cap_matrix_is_diagonal_in_r_and_matches_adaptive_quadrature, 1.0)
