@@ -215,6 +215,22 @@ def windows_leg(torch, api, f_t, g_single, steps, warmup, n_windows=4):
             "value": n_windows * wl.samples / (ms * 1e-3), "unit": "samples/s"}
 
 
+def slepian_leg(api):
+    """Slepian window generator: the paper's region R_(pi/6, pi/6 + pi/240) at L_h = 18 and
+    the largest band-limit, L_h = 32 (concentration matrix on the GPU, eigenvector on the
+    host); wall time per call."""
+    import math
+    out = {}
+    for L_h in (18, 32):
+        api.slepian_window(L_h, math.pi / 6, math.pi / 6 + math.pi / 240)
+        t = time.perf_counter()
+        _, lam = api.slepian_window(L_h, math.pi / 6, math.pi / 6 + math.pi / 240)
+        out[f"L_h={L_h}"] = {"ms": (time.perf_counter() - t) * 1e3, "concentration": lam}
+        log(f"slepian window L_h={L_h}: {out[f'L_h={L_h}']['ms']:.1f} ms, lambda {lam:.6f}")
+    out["region"] = "theta_c = pi/6, a = pi/6 + pi/240"
+    return out
+
+
 def serving_leg(n, rate):
     """Continuous batching of the serving workload: n requests with Poisson arrivals at
     `rate` req/s, L_f in {32..192}, L_h in {4,8,16}, width-8 l-windows, half FP64 and half
@@ -359,6 +375,7 @@ def main():
 
     line["steerable_mid"] = steerable_leg(torch, api, args.steps, args.warmup)
     line["windows_mid"] = windows_leg(torch, api, f_t, outputs["fp64"], args.steps, args.warmup)
+    line["slepian_window"] = slepian_leg(api)
 
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM

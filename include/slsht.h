@@ -175,6 +175,19 @@ int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n
  * h_0^0 != 0 (SLSHT_EINVAL otherwise).  Asynchronous after the h_0^0 read. */
 int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream);
 
+/* Slepian eigenfunction window (Section III-D): among functions band-limited to
+ * s < L_h, the one with the largest energy concentration in the elliptical region
+ * R_(theta_c, a) = {x : dist(x, (theta_c, 0)) + dist(x, (theta_c, pi)) <= 2a}
+ * (eq. Eq:region_def), 0 <= theta_c < a <= pi/2 (theta_c = 0: polar cap of radius a).
+ * The concentration matrix is summed by quadrature on `device` in FP64, its top
+ * eigenvector found on the host; synchronous.
+ *   h_out: host complex128[L_h * L_h], unit energy, real-signal consistent
+ *          (h_s^{-r} = (-1)^r conj(h_s^r)), sign fixed by a positive largest entry
+ *   concentration: host, int_R |h|^2 (may be NULL)
+ * SLSHT_EINVAL for arguments outside those ranges. */
+int slsht_slepian_window(int L_h, double theta_c, double a, int device, void* h_out,
+                         double* concentration);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of forward transforms of uneven size.
  *

@@ -30,6 +30,17 @@ def desc_for(wl, **over) -> L.Desc:
     return make_desc(wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta, wl.n_omega, **kw)
 
 
+def slepian_window(L_h: int, theta_c: float, a: float, device: int = 0):
+    """(h, concentration): the Slepian window of band-limit L_h most concentrated in the
+    elliptical region R_(theta_c, a), as a host complex128 array [L_h^2]."""
+    import numpy as np
+    h = np.zeros(L_h * L_h, dtype=np.complex128)
+    c = ctypes.c_double()
+    L.check(L.lib().slsht_slepian_window(L_h, theta_c, a, device, h.ctypes.data,
+                                         ctypes.byref(c)))
+    return h, c.value
+
+
 def validate(desc: L.Desc) -> None:
     L.check(L.lib().slsht_validate(ctypes.byref(desc)))
 

@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslsht.so")
-SOURCES = ["slsht_kernels.hip", "slsht_synth.hip", "slsht_energy.hip", "slsht_api.cpp",
-           "slsht_server.cpp"]
+SOURCES = ["slsht_kernels.hip", "slsht_synth.hip", "slsht_energy.hip", "slsht_slepian.hip",
+           "slsht_api.cpp", "slsht_server.cpp"]
 
 
 def hipcc() -> str:

@@ -430,6 +430,20 @@ int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n
     return SLSHT_OK;
 }
 
+int slsht_slepian_window(int L_h, double theta_c, double a, int device, void* h_out,
+                         double* concentration) {
+    if (!h_out) return slsht::set_error(SLSHT_EINVAL, "h_out is NULL");
+    if (L_h < 1 || L_h > SLSHT_MAX_LH)
+        return slsht::set_error(SLSHT_EINVAL, "L_h=%d outside [1, %d]", L_h, SLSHT_MAX_LH);
+    if (!(theta_c >= 0.0) || !(a > theta_c) || !(a <= 0.5 * M_PI + 1e-12))
+        return slsht::set_error(SLSHT_EINVAL, "need 0 <= theta_c < a <= pi/2 (got %g, %g)",
+                                theta_c, a);
+    DeviceGuard guard(device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice(%d) failed", device);
+    return slsht::slepian_window(L_h, theta_c, std::min(a, 0.5 * M_PI), (double2*)h_out,
+                                 concentration);
+}
+
 int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream) {
     if (!plan || !g || !h || !f_out) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
     const slsht::DevPlan& P = plan->P;

@@ -81,6 +81,8 @@ size_t device_lds_limit(int device);
 // Launchers; each returns hipSuccess or the launch error.
 hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s);
 hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipStream_t s);
+// Slepian window on R_(theta_c, a) (current device); h_out host complex128[L*L].
+int slepian_window(int L, double theta_c, double a, double2* h_out, double* concentration);
 hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
                             hipStream_t s);
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,

@@ -95,6 +95,18 @@ def test_steerable_window_rules(lib):
     assert ctypes.sizeof(L.Desc) == 13 * 4
 
 
+def test_slepian_window_argument_checks(lib):
+    """Rejected on the host before any GPU work: 0 <= theta_c < a <= pi/2, 1 <= L_h <= 32."""
+    import numpy as np
+    h = np.zeros(64, dtype=np.complex128)
+    c = ctypes.c_double()
+    for L_h, tc, a in ((8, 0.5, 0.5), (8, -0.1, 0.5), (8, 0.2, 2.0), (0, 0.1, 0.5),
+                       (33, 0.1, 0.5), (8, float("nan"), 0.5)):
+        assert lib.slsht_slepian_window(L_h, tc, a, 0, h.ctypes.data,
+                                        ctypes.byref(c)) == L.SLSHT_EINVAL, (L_h, tc, a)
+    assert lib.slsht_slepian_window(8, 0.1, 0.5, 0, None, None) == L.SLSHT_EINVAL
+
+
 def test_coupling_size(lib):
     d = api.desc_for(workload("mid"))
     assert lib.slsht_coupling_size(ctypes.byref(d)) == 1280 * 64
