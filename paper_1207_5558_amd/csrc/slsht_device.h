@@ -87,6 +87,15 @@ __device__ __forceinline__ void theta_item(int r, int L, int N, int& s, int& q, 
     s = aq > qp ? aq : qp;
 }
 
+// Item of thread `tid` in round j of a block-wide loop over `total` items (valid when
+// tid < min(nth, total - j*nth)).  Rounds alternate direction: with items sorted by trip
+// count, a thread's long items pair with short ones and the per-thread totals even out.
+__device__ __forceinline__ int snake_item(int j, int tid, int nth, int total) {
+    const int base = j * nth;
+    const int cnt = total - base < nth ? total - base : nth;
+    return base + ((j & 1) ? cnt - 1 - tid : tid);
+}
+
 // Canonical table entry of d^p_{q,q'}: d_{q,q'} = sign * d_{Q,Q'} with Q = max(|q|,|q'|)
 // >= |Q'|, from d_{q,q'} = (-1)^{q-q'} d_{q',q} = d_{-q',-q} (symmetries of Section IV-B).
 __device__ __forceinline__ void d_canonical(int q, int qp, int& Q, int& Qp, bool& neg) {

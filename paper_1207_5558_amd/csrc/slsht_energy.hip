@@ -99,9 +99,10 @@ __global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyA
         __syncthreads();
 
         // stage 1: theta contraction over |q'| < N (see theta_item / theta_pair)
-        for (int r = tid; r < nrep; r += nth) {
+        for (int j = 0; j * nth < nrep; ++j) {
+            if (tid >= nrep - j * nth) break;
             int s_, q, qp;
-            theta_item(r, L, a.N, s_, q, qp);
+            theta_item(snake_item(j, tid, nth, nrep), L, a.N, s_, q, qp);
             float2 v, vm;
             theta_pair<float, float2, 4>(D_s, A_s, h_s, L, s_, q, qp, v, vm);
             S_s[(q + L - 1) * K + (qp + L - 1)] = v;

@@ -190,7 +190,9 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     const T* dt = reinterpret_cast<const T*>(a.dtab);
     const int KK = K * K;
     const int nrep = theta_items(L, a.N);
-    for (int idx = tid; idx < tb * nrep; idx += nth) {
+    for (int j = 0; j * nth < tb * nrep; ++j) {
+        if (tid >= tb * nrep - j * nth) break;
+        const int idx = snake_item(j, tid, nth, tb * nrep);
         const int t = idx / nrep;
         int s_, q, qp;
         theta_item(idx - t * nrep, L, a.N, s_, q, qp);

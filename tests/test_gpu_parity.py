@@ -151,3 +151,28 @@ def test_largest_window_band_limit(prec, tol):
     got = gather_rho(g, idx_local)
     errs = per_l_rel_err(got, ref, l_lo, l_hi, axis=1)
     assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("L_h", [16, 20])
+@pytest.mark.parametrize("prec,tol,pair", [("fp64", FP64_TOL, False), ("fp64", FP64_TOL, True),
+                                           ("fp32", FP32_TOL, True)])
+def test_matrix_core_phi_stage_sampled(L_h, prec, tol, pair):
+    """L_h >= 16 runs the phi stage on MFMA: 151 phi samples give two 64-slot units, the
+    second partial; real pair writes the m < 0 rows from the transposed fragments."""
+    announce(f"MFMA phi stage L_h={L_h} {prec} pair={pair}")
+    rng = np.random.default_rng(17)
+    L_f, l_lo, l_hi, n_phi, n_omega = 6, 14, 17, 151, 7
+    f = draw_coefficients(rng, L_f, 0.0)
+    h = draw_window(rng, L_h)
+    n_theta = (n_phi + 1) // 2
+    plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, precision=prec,
+                                  real_pair=pair))
+    g = plan.forward(dev(f), dev(h))
+    idx = np.stack([rng.integers(0, n_phi, 160), rng.integers(0, n_theta, 160),
+                    rng.integers(0, n_omega, 160)], 1)
+    idx[0] = (0, 0, 0)
+    idx[1] = (n_phi - 1, n_theta - 1, n_omega - 1)
+    idx[2] = (75, n_theta - 1, 3)
+    ref = oracle_g_grid(f, h, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, idx)
+    errs = per_l_rel_err(gather_rho(g, idx), ref, l_lo, l_hi, axis=1)
+    assert max(errs.values()) <= tol, errs
