@@ -275,6 +275,8 @@ def main():
     ap.add_argument("--no-energy", action="store_true", help="skip the ENERGY workload leg")
     ap.add_argument("--steps-energy", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the steerable-window, several-window and Slepian-window legs")
     ap.add_argument("--serve-n", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, req/s")
     ap.add_argument("--serve-rate-sat", type=float, default=20000.0,
@@ -373,9 +375,11 @@ def main():
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": alg32 / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
-    line["steerable_mid"] = steerable_leg(torch, api, args.steps, args.warmup)
-    line["windows_mid"] = windows_leg(torch, api, f_t, outputs["fp64"], args.steps, args.warmup)
-    line["slepian_window"] = slepian_leg(api)
+    if not args.no_next:
+        line["steerable_mid"] = steerable_leg(torch, api, args.steps, args.warmup)
+        line["windows_mid"] = windows_leg(torch, api, f_t, outputs["fp64"], args.steps,
+                                          args.warmup)
+        line["slepian_window"] = slepian_leg(api)
 
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM
