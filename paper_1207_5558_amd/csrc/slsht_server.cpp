@@ -14,6 +14,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -99,10 +100,20 @@ struct slsht_server_s {
         }
     }
 
+    // Keeps the table cache bounded: beyond kMaxTables entries, drops the sets that no
+    // request holds (a request's plan keeps its own reference until it is released).
+    static constexpr size_t kMaxTables = 64;
+    void trim_tables() {
+        if (tables.size() <= kMaxTables) return;
+        for (auto it = tables.begin(); it != tables.end() && tables.size() > kMaxTables;)
+            it = it->second.use_count() == 1 ? tables.erase(it) : std::next(it);
+    }
+
     int launch(Request& r) {
         const std::string key = slsht::tables_key(r.d);
         auto it = tables.find(key);
         if (it == tables.end()) {
+            trim_tables();
             std::shared_ptr<slsht::Tables> T;
             int rc = slsht::build_tables(r.d, device, T);
             if (rc) return rc;

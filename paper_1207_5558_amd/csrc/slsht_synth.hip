@@ -518,6 +518,7 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
     a.xsize = (int)synth_xsize(P, P.tb);
     a.N = n_az_of(P.d);
     const int64_t nblk = (int64_t)P.n_items * a.n_tiles;
+    if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;   // grid.x limit
     void* args[] = {&a};
     return hipLaunchKernel(synth_fn(P), dim3((unsigned)nblk), dim3(P.block), args, P.lds_bytes, s);
 }
