@@ -231,6 +231,41 @@ def slepian_leg(api):
     return out
 
 
+def factored_leg(torch, api, L_h=18, L_fs=(18, 34, 66, 130)):
+    """The paper's timing experiment shape (tau_2: every g(rho; l, m), l < L_f + L_h - 1, on
+    the minimal grid E_{L_h}, given the coupling), L_h = 18 as in its validation: the
+    factoring-of-rotations route against the separated-form kernel, FP64."""
+    from paper_1207_5558_amd.inputs import draw_coefficients, draw_window
+    rng = np.random.default_rng(5)
+    h = torch.from_numpy(draw_window(rng, L_h)).to("cuda:0")
+    K = 2 * L_h - 1
+    out = {"workload": f"L_h={L_h}, all l < L_f + L_h - 1, minimal grid {K} x {L_h} x {K}, FP64",
+           "points": []}
+    for L_f in L_fs:
+        f = torch.from_numpy(draw_coefficients(rng, L_f, 2.0, True)).to("cuda:0")
+        plan = api.Plan(api.make_desc(L_f, L_h, 0, L_f + L_h - 1, K, L_h, K), device=0)
+        g = plan.empty_output()
+        work = torch.empty(api.factored_workspace(plan.desc), dtype=torch.uint8, device="cuda:0")
+        res = {}
+        for name, fn in (("factored_ms", lambda: plan.forward_factored(f, h, g, work)),
+                         ("separated_ms", lambda: plan.forward(f, h, g))):
+            fn()
+            torch.cuda.synchronize()
+            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_.record()
+            for _ in range(3):
+                fn()
+            e_.record()
+            torch.cuda.synchronize()
+            res[name] = s_.elapsed_time(e_) / 3
+        out["points"].append({"L_f": L_f, "n_lm": plan.n_lm, **res})
+        log(f"factored route L_f={L_f}: {res['factored_ms']:.3f} ms, separated "
+            f"{res['separated_ms']:.3f} ms")
+        del g, work, plan
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(n, rate):
     """Continuous batching of the serving workload: n requests with Poisson arrivals at
     `rate` req/s, L_f in {32..192}, L_h in {4,8,16}, width-8 l-windows, half FP64 and half
@@ -380,6 +415,7 @@ def main():
         line["windows_mid"] = windows_leg(torch, api, f_t, outputs["fp64"], args.steps,
                                           args.warmup)
         line["slepian_window"] = slepian_leg(api)
+        line["factored_route"] = factored_leg(torch, api)
 
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM

@@ -175,6 +175,21 @@ int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n
  * h_0^0 != 0 (SLSHT_EINVAL otherwise).  Asynchronous after the h_0^0 read. */
 int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream);
 
+/* The paper's own route, for comparison (factoring of rotations, Section IV-B):
+ * on its minimal grid E_{L_h} (n_phi = n_omega = 2 L_h - 1, n_theta = L_h), g is a
+ * 3-D Fourier sum of
+ *   C_{q,q'',q'}(l,m) = i^{q-q'} sum_p A^p_q h_p^{q'} Delta^p_{q'',q} Delta^p_{q'',q'},
+ * Delta^p = d^p(pi/2) (eq. Eq:WignerD_expansion_new).  Computed in FP64 as plain passes
+ * (C, then the omega, theta and phi sums) over a caller-provided workspace.
+ * slsht_factored_workspace(desc): bytes needed, or -1 (SLSHT_EINVAL in
+ * slsht_last_error) unless desc is FULL, FP64, on that grid, over all theta rows,
+ * without flags or a steerable limit, with at most 65535 (l, m).
+ * slsht_forward_factored: same f, h, g as slsht_forward on such a plan; work is
+ * device memory of at least work_bytes >= slsht_factored_workspace(); asynchronous. */
+int64_t slsht_factored_workspace(const slsht_desc* desc);
+int slsht_forward_factored(slsht_plan_t plan, const void* f, const void* h, void* g, void* work,
+                           size_t work_bytes, void* stream);
+
 /* Slepian eigenfunction window (Section III-D): among functions band-limited to
  * s < L_h, the one with the largest energy concentration in the elliptical region
  * R_(theta_c, a) = {x : dist(x, (theta_c, 0)) + dist(x, (theta_c, pi)) <= 2a}

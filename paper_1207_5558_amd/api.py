@@ -41,6 +41,15 @@ def slepian_window(L_h: int, theta_c: float, a: float, device: int = 0):
     return h, c.value
 
 
+def factored_workspace(desc: L.Desc) -> int:
+    """Bytes of device workspace slsht_forward_factored needs for desc (raises if desc is
+    not eligible for the factoring-of-rotations route)."""
+    need = L.lib().slsht_factored_workspace(ctypes.byref(desc))
+    if need < 0:
+        raise L.SlshtError(L.SLSHT_EINVAL, L.last_error())
+    return need
+
+
 def validate(desc: L.Desc) -> None:
     L.check(L.lib().slsht_validate(ctypes.byref(desc)))
 
@@ -155,6 +164,25 @@ class Plan:
             self._h, _dev_ptr(f, torch.complex128, d.L_f * d.L_f, "f"),
             _dev_ptr(h, torch.complex128, W * d.L_h * d.L_h, "h"), W,
             _dev_ptr(g, self.output_dtype, n_out, "g"), _stream_handle(stream)))
+        return g
+
+    def forward_factored(self, f: torch.Tensor, h: torch.Tensor, g: torch.Tensor | None = None,
+                         work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """The paper's factoring-of-rotations route (plans on the minimal grid only)."""
+        d = self.desc
+        need = factored_workspace(d)
+        if g is None:
+            g = self.empty_output()
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        n_out = 1
+        for s in self.output_shape:
+            n_out *= s
+        L.check(L.lib().slsht_forward_factored(
+            self._h, _dev_ptr(f, torch.complex128, d.L_f * d.L_f, "f"),
+            _dev_ptr(h, torch.complex128, d.L_h * d.L_h, "h"),
+            _dev_ptr(g, self.output_dtype, n_out, "g"),
+            _dev_ptr(work, torch.uint8, need, "work"), need, _stream_handle(stream)))
         return g
 
     def inverse(self, g: torch.Tensor, h: torch.Tensor, f_out: torch.Tensor | None = None,

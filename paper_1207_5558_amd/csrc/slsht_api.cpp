@@ -430,6 +430,42 @@ int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n
     return SLSHT_OK;
 }
 
+static bool factored_eligible(const slsht_desc& d) {
+    return d.output_mode == SLSHT_OUT_FULL && d.precision == SLSHT_FP64 && d.flags == 0 &&
+           (d.n_az == 0 || d.n_az == d.L_h) && d.n_phi == 2 * d.L_h - 1 &&
+           d.n_omega == 2 * d.L_h - 1 && d.theta_lo == 0 && theta_hi_of(d) == d.n_theta &&
+           (int64_t)d.l_hi * d.l_hi - (int64_t)d.l_lo * d.l_lo <= 65535;
+}
+
+int64_t slsht_factored_workspace(const slsht_desc* desc) {
+    if (slsht::check_desc(desc) != SLSHT_OK) return -1;
+    if (!factored_eligible(*desc)) {
+        slsht::set_error(SLSHT_EINVAL, "the factored route needs a FULL FP64 plan on the minimal "
+                                       "grid n_phi = n_omega = 2 L_h - 1, all theta rows, no flags, "
+                                       "at most 65535 (l, m)");
+        return -1;
+    }
+    return (int64_t)slsht::factored_workspace_bytes(*desc);
+}
+
+int slsht_forward_factored(slsht_plan_t plan, const void* f, const void* h, void* g, void* work,
+                           size_t work_bytes, void* stream) {
+    if (!plan || !f || !h || !g || !work) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
+    const slsht::DevPlan& P = plan->P;
+    const int64_t need = slsht_factored_workspace(&P.d);
+    if (need < 0) return SLSHT_EINVAL;
+    if (work_bytes < (size_t)need)
+        return slsht::set_error(SLSHT_EINVAL, "workspace of %zu bytes, needs %lld", work_bytes,
+                                (long long)need);
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = slsht::launch_coupling(P, (const double2*)f, P.A, s);
+    if (e == hipSuccess) e = slsht::launch_factored(P, P.A, (const double2*)h, (double2*)g, work, s);
+    if (e != hipSuccess) return hip_fail(e, "factored route launch");
+    return SLSHT_OK;
+}
+
 int slsht_slepian_window(int L_h, double theta_c, double a, int device, void* h_out,
                          double* concentration) {
     if (!h_out) return slsht::set_error(SLSHT_EINVAL, "h_out is NULL");

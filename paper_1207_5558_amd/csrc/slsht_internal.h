@@ -18,7 +18,7 @@ namespace slsht {
 // 0 <= Q <= p, -Q <= Q' <= Q, at dtab_off(p) + Q^2 + Q + Q'; every other (q, q')
 // follows from d_{q,q'} = (-1)^{q-q'} d_{q',q} = d_{-q',-q} (Section IV-B).
 // Entries per row: sum_{p<L} (p+1)^2 = L(L+1)(2L+1)/6, a quarter of the full set.
-inline int64_t dtab_row_len(int L) { return (int64_t)L * (L + 1) * (2 * L + 1) / 6; }
+__host__ __device__ inline int64_t dtab_row_len(int L) { return (int64_t)L * (L + 1) * (2 * L + 1) / 6; }
 // Offset of degree p inside one theta row of the table.
 __host__ __device__ inline int dtab_off(int p) { return p * (p + 1) * (2 * p + 1) / 6; }
 
@@ -81,6 +81,11 @@ size_t device_lds_limit(int device);
 // Launchers; each returns hipSuccess or the launch error.
 hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s);
 hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipStream_t s);
+// Factoring-of-rotations route on the minimal grid (slsht_factored.hip).
+hipError_t launch_delta_table(int L, double* out, hipStream_t s);
+size_t factored_workspace_bytes(const slsht_desc& d);
+hipError_t launch_factored(const DevPlan& P, const double2* A, const double2* h, double2* g,
+                           void* work, hipStream_t s);
 // Slepian window on R_(theta_c, a) (current device); h_out host complex128[L*L].
 int slepian_window(int L, double theta_c, double a, double2* h_out, double* concentration);
 hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,

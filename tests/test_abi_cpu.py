@@ -107,6 +107,19 @@ def test_slepian_window_argument_checks(lib):
     assert lib.slsht_slepian_window(8, 0.1, 0.5, 0, None, None) == L.SLSHT_EINVAL
 
 
+def test_factored_route_workspace(lib):
+    """Host-only eligibility and size of the factoring-of-rotations workspace."""
+    d = api.make_desc(8, 3, 0, 10, 5, 3, 5)                      # minimal grid, K = 5
+    n_lm, K, row = 100, 5, 3 * 4 * 7 // 6
+    delta = (row * 8 + 255) // 256 * 256
+    assert lib.slsht_factored_workspace(ctypes.byref(d)) == delta + 2 * n_lm * K ** 3 * 16
+    for bad in (api.make_desc(8, 3, 0, 10, 21, 11, 5),          # not the minimal grid
+                api.make_desc(8, 3, 0, 10, 5, 3, 5, precision="fp32"),
+                api.make_desc(8, 3, 0, 10, 5, 3, 5, real_pair=True),
+                api.make_desc(8, 3, 0, 10, 5, 3, 5, theta_lo=1)):
+        assert lib.slsht_factored_workspace(ctypes.byref(bad)) == -1
+
+
 def test_coupling_size(lib):
     d = api.desc_for(workload("mid"))
     assert lib.slsht_coupling_size(ctypes.byref(d)) == 1280 * 64
