@@ -12,10 +12,14 @@ namespace slsht {
 // ------------------------------------------------------------------------------
 // K3e: energy epilogue, FP32.  One block = one degree l x one theta row; the order m
 // runs inside the block and E(phi_a, theta_b, omega_c; l) = sum_m |g|^2 stays in
-// registers until all orders are done, so g is never written.  Per m:
-//   stage 1 (VALU): S_{q,q'}(theta_b) as in K3                              -> LDS
-//   stage 2 (VALU): omega synthesis folded into P_k, M_k, stored k-major with
-//                   omega contiguous (the B operand layout of the MFMA below)  -> LDS
+// registers until all orders are done, so g is never written.  The block's canonical
+// Wigner-d row is staged in LDS once.  Per m:
+//   stage 1 (VALU): S_{q,q'}(theta_b) as in K3, d read from LDS          -> LDS
+//   stage 2 (MFMA + VALU): omega synthesis as folded real GEMMs
+//                   X[q][c] = S[q][0] + sum_k (S[q][k] + S[q][-k]) cos(k omega_c),
+//                   Y[q][c] = sum_k (S[q][k] - S[q][-k]) sin(k omega_c), then the fold
+//                   into P_k, M_k, stored k-major with omega contiguous (the B operand
+//                   layout of stage 3)                                        -> LDS
 //   stage 3 (MFMA): the phi synthesis is a real GEMM per part (Re, Im) and per
 //                   cos/sin half:  C[a][c] = sum_k cos(k phi_a) P_k(c),
 //                   S[a][c] = sum_k sin(k phi_a) M_k(c)   (16x16x4 FP32 MFMA),

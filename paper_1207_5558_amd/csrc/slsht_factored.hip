@@ -154,6 +154,9 @@ hipError_t launch_factored(const DevPlan& P, const double2* A, const double2* h,
     hipError_t e = launch_delta_table(L, delta, s);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)2 * L * L * sizeof(double2) + (size_t)dtab_row_len(L) * sizeof(double);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)factored_c_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(factored_c_kernel, dim3((unsigned)n_lm), dim3(256), lds, s, A, h, delta, L, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t KKK = (int64_t)K * K * K, KLK = (int64_t)K * L * K;

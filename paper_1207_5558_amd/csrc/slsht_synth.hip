@@ -21,7 +21,7 @@ namespace slsht {
 // The cosine/sine folding uses phi_{n-a} = -phi_a (mod 2 pi), so one product makes
 // two outputs; stage 2 folds omega the same way.  For L_h <= 8 stage 3 runs on the
 // VALU: a lane keeps cos/sin(q phi_a) of its slots in registers and reads U_0, P_q, M_q
-// as LDS broadcasts.  For L_h >= 16 those broadcasts would bound it, and stage 3 is a
+// as LDS broadcasts.  For L_h > 8 those broadcasts would bound it, and stage 3 is a
 // pair of real GEMMs on the matrix cores, one row per (omega_c, theta_b, Re|Im) and
 // one column per slot a:
 //   C = Pmat (rows x k) * cos(k phi_a) (k x a),   S = Mmat * sin(k phi_a),
