@@ -218,7 +218,7 @@ def windows_leg(torch, api, f_t, g_single, steps, warmup, n_windows=4):
 def slepian_leg(api):
     """Slepian window generator: the paper's region R_(pi/6, pi/6 + pi/240) at L_h = 18 and
     the largest band-limit, L_h = 32 (concentration matrix on the GPU, eigenvector on the
-    host); wall time per call."""
+    host by Householder tridiagonalisation and implicit QL); wall time per call."""
     import math
     out = {}
     for L_h in (18, 32):

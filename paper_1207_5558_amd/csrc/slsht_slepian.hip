@@ -8,8 +8,9 @@
 // of r.  Its entries
 //   D = c_r c_r' sum_j w_j lam_s^r(theta_j) lam_s'^r'(theta_j) (J_{|r-r'|}(theta_j) +- J_{r+r'}(theta_j)) / 2,
 // with J_k(theta) = int over the region's phi set at theta of cos(k phi), are summed on
-// the GPU in FP64 (one thread per entry); the top eigenvector of each block comes from
-// cyclic Jacobi rotations on the host, and the best of the four is the window.
+// the GPU in FP64 (one thread per entry); the top eigenvector of each block comes from a
+// Householder reduction to tridiagonal form and implicit QL iterations on the host, and
+// the best of the four is the window.
 //
 // Quadrature in theta: [0, b] (cos b = cos a / cos theta_c) is the part where the whole
 // circle lies in R, so J_k = 2 pi delta_k0 and the integrand is a polynomial in
@@ -122,51 +123,116 @@ double phi_half_width(double theta, double tc, double a) {
     return 0.5 * (lo + hi);
 }
 
-// Top eigenpair of a real symmetric n x n matrix (row-major, destroyed) by cyclic
-// Jacobi rotations.
-double jacobi_top(std::vector<double>& A, int n, std::vector<double>& vec) {
-    std::vector<double> V((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int p = 0; p < n; ++p)
-            for (int q = 0; q < n; ++q) {
-                const double v = A[(size_t)p * n + q] * A[(size_t)p * n + q];
-                tot += v;
-                if (p != q) off += v;
+// Top eigenpair of a real symmetric matrix: Householder reduction to tridiagonal form
+// (accumulating the orthogonal transform), then implicit QL with Wilkinson shifts on
+// the tridiagonal matrix, rotating the accumulated transform.
+double sym_top(std::vector<double>& A, int n, std::vector<double>& vec) {   // A row-major, destroyed
+    // Householder: A = Q T Q^T, T tridiagonal with diagonal d, off-diagonal e
+    std::vector<double> d(n), e(n, 0.0);
+    auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+    for (int i = n - 1; i > 0; --i) {
+        const int l = i - 1;
+        double h = 0.0, scale = 0.0;
+        if (l > 0) {
+            for (int k = 0; k <= l; ++k) scale += std::fabs(a(i, k));
+            if (scale == 0.0) {
+                e[i] = a(i, l);
+            } else {
+                for (int k = 0; k <= l; ++k) {
+                    a(i, k) /= scale;
+                    h += a(i, k) * a(i, k);
+                }
+                double f = a(i, l);
+                double g = f >= 0.0 ? -std::sqrt(h) : std::sqrt(h);
+                e[i] = scale * g;
+                h -= f * g;
+                a(i, l) = f - g;
+                f = 0.0;
+                for (int j = 0; j <= l; ++j) {
+                    a(j, i) = a(i, j) / h;
+                    g = 0.0;
+                    for (int k = 0; k <= j; ++k) g += a(j, k) * a(i, k);
+                    for (int k = j + 1; k <= l; ++k) g += a(k, j) * a(i, k);
+                    e[j] = g / h;
+                    f += e[j] * a(i, j);
+                }
+                const double hh = f / (h + h);
+                for (int j = 0; j <= l; ++j) {
+                    f = a(i, j);
+                    e[j] = g = e[j] - hh * f;
+                    for (int k = 0; k <= j; ++k) a(j, k) -= (f * e[k] + g * a(i, k));
+                }
             }
-        if (off <= 1e-30 * tot || off == 0.0) break;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = A[(size_t)p * n + q];
-                if (fabs(apq) < 1e-300) continue;
-                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-                const double th = (aqq - app) / (2.0 * apq);
-                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < n; ++k) {             // columns p, q
-                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-                    A[(size_t)k * n + p] = c * akp - s * akq;
-                    A[(size_t)k * n + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < n; ++k) {             // rows p, q
-                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-                    A[(size_t)p * n + k] = c * apk - s * aqk;
-                    A[(size_t)q * n + k] = s * apk + c * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-                    V[(size_t)k * n + p] = c * vkp - s * vkq;
-                    V[(size_t)k * n + q] = s * vkp + c * vkq;
-                }
+        } else {
+            e[i] = a(i, l);
+        }
+        d[i] = h;
+    }
+    d[0] = 0.0;
+    e[0] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const int l = i - 1;
+        if (d[i] != 0.0) {
+            for (int j = 0; j <= l; ++j) {
+                double g = 0.0;
+                for (int k = 0; k <= l; ++k) g += a(i, k) * a(k, j);
+                for (int k = 0; k <= l; ++k) a(k, j) -= g * a(k, i);
             }
+        }
+        d[i] = a(i, i);
+        a(i, i) = 1.0;
+        for (int j = 0; j <= l; ++j) a(j, i) = a(i, j) = 0.0;
+    }
+    // QL with implicit shifts; A now holds Q (columns are the basis)
+    for (int i = 1; i < n; ++i) e[i - 1] = e[i];
+    e[n - 1] = 0.0;
+    for (int l = 0; l < n; ++l) {
+        int iter = 0, m;
+        do {
+            for (m = l; m < n - 1; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 1e-16 * dd) break;
+            }
+            if (m != l) {
+                if (++iter > 60) break;
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = std::hypot(g, 1.0);
+                g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? std::fabs(r) : -std::fabs(r)));
+                double s = 1.0, c = 1.0, p = 0.0;
+                int i;
+                for (i = m - 1; i >= l; --i) {
+                    double f = s * e[i], b = c * e[i];
+                    e[i + 1] = (r = std::hypot(f, g));
+                    if (r == 0.0) {
+                        d[i + 1] -= p;
+                        e[m] = 0.0;
+                        break;
+                    }
+                    s = f / r;
+                    c = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * c * b;
+                    d[i + 1] = g + (p = s * r);
+                    g = c * r - b;
+                    for (int k = 0; k < n; ++k) {
+                        f = a(k, i + 1);
+                        a(k, i + 1) = s * a(k, i) + c * f;
+                        a(k, i) = c * a(k, i) - s * f;
+                    }
+                }
+                if (r == 0.0 && i >= l) continue;
+                d[l] -= p;
+                e[l] = g;
+                e[m] = 0.0;
+            }
+        } while (m != l);
     }
     int best = 0;
     for (int i = 1; i < n; ++i)
-        if (A[(size_t)i * n + i] > A[(size_t)best * n + best]) best = i;
+        if (d[i] > d[best]) best = i;
     vec.resize(n);
-    for (int k = 0; k < n; ++k) vec[k] = V[(size_t)k * n + best];
-    return A[(size_t)best * n + best];
+    for (int k = 0; k < n; ++k) vec[k] = a(k, best);
+    return d[best];
 }
 
 }  // namespace
@@ -252,7 +318,7 @@ int slepian_window(int L, double tc, double a, double2* h_out, double* conc) {
         ok(hipMemcpy(A.data(), dD, A.size() * sizeof(double), hipMemcpyDeviceToHost));
         if (e != hipSuccess) break;
         std::vector<double> v;
-        const double lam = jacobi_top(A, nb, v);
+        const double lam = sym_top(A, nb, v);
         if (lam > best) { best = lam; bestvec = v; bestb = bi; }
     }
     for (void* p : {(void*)dx, (void*)dw, (void*)dJ, (void*)dlam, (void*)dD, (void*)dbs, (void*)dbr})
