@@ -232,37 +232,59 @@ def slepian_leg(api):
 
 
 def factored_leg(torch, api, L_h=18, L_fs=(18, 34, 66, 130)):
-    """The paper's timing experiment shape (tau_2: every g(rho; l, m), l < L_f + L_h - 1, on
-    the minimal grid E_{L_h}, given the coupling), L_h = 18 as in its validation: the
-    factoring-of-rotations route against the separated-form kernel, FP64."""
+    """The paper's timing experiment (Section V), L_h = 18, every g(rho; l, m) for
+    l < L_f + L_h - 1 on the minimal grid E_{L_h}, FP64: tau_1 = coupling through the
+    modulated-signal transform (Appendix A), tau_2 = factored synthesis from it (Delta by
+    the Trapani-Navaza recursion, C, 3-D Fourier sum), tau_3 = inverse; beside them the
+    3j coupling and the separated-form forward (coupling + synthesis) on the same grid.
+    Log-log slopes between the last two points are reported for comparison with the
+    paper's O(L_f^3) (tau_1) and O(L_f^2) (tau_2, tau_3)."""
     from paper_1207_5558_amd.inputs import draw_coefficients, draw_window
     rng = np.random.default_rng(5)
     h = torch.from_numpy(draw_window(rng, L_h)).to("cuda:0")
     K = 2 * L_h - 1
     out = {"workload": f"L_h={L_h}, all l < L_f + L_h - 1, minimal grid {K} x {L_h} x {K}, FP64",
            "points": []}
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_.record()
+        for _ in range(reps):
+            fn()
+        e_.record()
+        torch.cuda.synchronize()
+        return s_.elapsed_time(e_) / reps
+
     for L_f in L_fs:
         f = torch.from_numpy(draw_coefficients(rng, L_f, 2.0, True)).to("cuda:0")
         plan = api.Plan(api.make_desc(L_f, L_h, 0, L_f + L_h - 1, K, L_h, K), device=0)
         g = plan.empty_output()
-        work = torch.empty(api.factored_workspace(plan.desc), dtype=torch.uint8, device="cuda:0")
-        res = {}
-        for name, fn in (("factored_ms", lambda: plan.forward_factored(f, h, g, work)),
-                         ("separated_ms", lambda: plan.forward(f, h, g))):
-            fn()
-            torch.cuda.synchronize()
-            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            s_.record()
-            for _ in range(3):
-                fn()
-            e_.record()
-            torch.cuda.synchronize()
-            res[name] = s_.elapsed_time(e_) / 3
+        A = torch.empty((plan.n_lm, L_h * L_h), dtype=torch.complex128, device="cuda:0")
+        A3 = torch.empty_like(A)
+        f_out = torch.empty(plan.n_lm, dtype=torch.complex128, device="cuda:0")
+        work_f = torch.empty(api.factored_workspace(plan.desc), dtype=torch.uint8, device="cuda:0")
+        work_m = torch.empty(api.modulated_workspace(plan.desc), dtype=torch.uint8,
+                             device="cuda:0")
+        res = {
+            "tau1_ms": timed(lambda: plan.coupling_modulated(f, A, work_m)),
+            "tau2_ms": timed(lambda: plan.synthesize_factored(A, h, g, work_f)),
+            "tau3_ms": timed(lambda: plan.inverse(g, h, f_out)),
+            "coupling_3j_ms": timed(lambda: plan.coupling(f, A3)),
+            "separated_ms": timed(lambda: plan.forward(f, h, g)),
+        }
         out["points"].append({"L_f": L_f, "n_lm": plan.n_lm, **res})
-        log(f"factored route L_f={L_f}: {res['factored_ms']:.3f} ms, separated "
-            f"{res['separated_ms']:.3f} ms")
-        del g, work, plan
+        log(f"paper route L_f={L_f}: tau1 {res['tau1_ms']:.3f} ms, tau2 {res['tau2_ms']:.3f} ms, "
+            f"tau3 {res['tau3_ms']:.3f} ms | 3j coupling {res['coupling_3j_ms']:.3f} ms, "
+            f"separated forward {res['separated_ms']:.3f} ms")
+        del g, A, A3, f_out, work_f, work_m, plan
         torch.cuda.empty_cache()
+    if len(out["points"]) >= 2:
+        p0, p1 = out["points"][-2], out["points"][-1]
+        r = np.log(p1["L_f"] / p0["L_f"])
+        for k in ("tau1", "tau2", "tau3"):
+            out[f"slope_{k}"] = float(np.log(p1[f"{k}_ms"] / p0[f"{k}_ms"]) / r)
     return out
 
 

@@ -179,16 +179,50 @@ int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, 
  * on its minimal grid E_{L_h} (n_phi = n_omega = 2 L_h - 1, n_theta = L_h), g is a
  * 3-D Fourier sum of
  *   C_{q,q'',q'}(l,m) = i^{q-q'} sum_p A^p_q h_p^{q'} Delta^p_{q'',q} Delta^p_{q'',q'},
- * Delta^p = d^p(pi/2) (eq. Eq:WignerD_expansion_new).  Computed in FP64 as plain passes
- * (C, then the omega, theta and phi sums) over a caller-provided workspace.
+ * Delta^p = d^p(pi/2) (eq. Eq:WignerD_expansion_new), evaluated on the fly by the
+ * recursion of Trapani and Navaza as the paper does.  Computed in FP64 as plain passes
+ * (Delta, C, then the omega, theta and phi sums) over a caller-provided workspace.
  * slsht_factored_workspace(desc): bytes needed, or -1 (SLSHT_EINVAL in
  * slsht_last_error) unless desc is FULL, FP64, on that grid, over all theta rows,
  * without flags or a steerable limit, with at most 65535 (l, m).
- * slsht_forward_factored: same f, h, g as slsht_forward on such a plan; work is
- * device memory of at least work_bytes >= slsht_factored_workspace(); asynchronous. */
+ * slsht_forward_factored: same f, h, g as slsht_forward on such a plan (coupling by
+ * slsht_coupling's 3j route, then the factored synthesis); work is device memory of at
+ * least work_bytes >= slsht_factored_workspace(); asynchronous.
+ * slsht_synthesize_factored: the factored synthesis alone from a given coupling
+ *   A: device complex128[slsht_coupling_size()], layout of slsht_coupling
+ * (the paper's tau_2 stage of its timing experiment, Section V); same rules. */
 int64_t slsht_factored_workspace(const slsht_desc* desc);
 int slsht_forward_factored(slsht_plan_t plan, const void* f, const void* h, void* g, void* work,
                            size_t work_bytes, void* stream);
+int slsht_synthesize_factored(slsht_plan_t plan, const void* A, const void* h, void* g,
+                              void* work, size_t work_bytes, void* stream);
+
+/* Delta^p_{Q,Q'} = d^p_{Q,Q'}(pi/2) for p < L_h, 0 <= Q <= p, -Q <= Q' <= Q, by the
+ * Trapani-Navaza recursion (Section IV-B): each column seeded on the edge Q = p by
+ * Wigner's formula, then run down in Q by the three-term relation of d at pi/2.
+ *   delta: device float64[L_h (L_h+1) (2 L_h+1) / 6], entry (p, Q, Q') at
+ *          p (p+1) (2p+1) / 6 + Q^2 + Q + Q'; the other entries follow from
+ *          Delta_{q,q'} = (-1)^{q-q'} Delta_{q',q} = Delta_{-q',-q}.
+ * 1 <= L_h <= SLSHT_MAX_LH (SLSHT_EINVAL otherwise).  Asynchronous on `stream` of
+ * `device`; the caller owns delta. */
+int slsht_wigner_delta(int L_h, int device, void* delta, void* stream);
+
+/* Coupling through the spherical harmonic transform of the modulated signal
+ * conj(f) Y_l^m (Appendix A, eq. Eq:sht_sep_variable): the paper's tau_1 stage.  Same
+ * result and layout as slsht_coupling (which uses 3j symbols instead):
+ *   A[lm][p*p + p + q] = 2 pi sum_j w_j lam_l^m(theta_j) lam_p^q(theta_j) F_{m-q}(theta_j),
+ *   F_mu(theta) = sum_{l'} f_{l'}^mu lam_{l'}^mu(theta),  lam_l^m Y_l^m's theta factor,
+ * summed over n = ((L_f-1) + (l_hi-1) + (L_h-1)) / 2 + 1 Gauss-Legendre nodes in
+ * cos(theta), exact for this integrand; FP64 for every plan precision.
+ * slsht_modulated_workspace(desc): bytes of device workspace (nodes, weights, F and
+ * the Legendre values of the l-window and of p < L_h), or -1 for an invalid desc.
+ * slsht_coupling_modulated: f device complex128[L_f * L_f]; A device
+ * complex128[slsht_coupling_size()]; work device memory of work_bytes >=
+ * slsht_modulated_workspace() (SLSHT_EINVAL otherwise).  Asynchronous on `stream`;
+ * the workspace may be reused once the call's work on the stream has finished. */
+int64_t slsht_modulated_workspace(const slsht_desc* desc);
+int slsht_coupling_modulated(slsht_plan_t plan, const void* f, void* A, void* work,
+                             size_t work_bytes, void* stream);
 
 /* Slepian eigenfunction window (Section III-D): among functions band-limited to
  * s < L_h, the one with the largest energy concentration in the elliptical region

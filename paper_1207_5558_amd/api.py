@@ -50,6 +50,24 @@ def factored_workspace(desc: L.Desc) -> int:
     return need
 
 
+def modulated_workspace(desc: L.Desc) -> int:
+    """Bytes of device workspace slsht_coupling_modulated needs for desc."""
+    need = L.lib().slsht_modulated_workspace(ctypes.byref(desc))
+    if need < 0:
+        raise L.SlshtError(L.SLSHT_EINVAL, L.last_error())
+    return need
+
+
+def wigner_delta(L_h: int, device: int = 0, stream=None):
+    """Delta^p = d^p(pi/2), p < L_h, canonical layout (float64 device tensor of
+    L_h (L_h+1)(2 L_h+1)/6 entries, p(p+1)(2p+1)/6 + Q^2 + Q + Q' for 0 <= Q <= p)."""
+    n = L_h * (L_h + 1) * (2 * L_h + 1) // 6
+    out = torch.empty(n, dtype=torch.float64, device=f"cuda:{device}")
+    L.check(L.lib().slsht_wigner_delta(L_h, device, _dev_ptr(out, torch.float64, n, "delta"),
+                                       _stream_handle(stream)))
+    return out
+
+
 def validate(desc: L.Desc) -> None:
     L.check(L.lib().slsht_validate(ctypes.byref(desc)))
 
@@ -147,6 +165,24 @@ class Plan:
                                        _stream_handle(stream)))
         return A
 
+    def coupling_modulated(self, f: torch.Tensor, A: torch.Tensor | None = None,
+                           work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """The coupling by the modulated-signal transform (the paper's Appendix A route);
+        same result and layout as coupling()."""
+        d = self.desc
+        n = self.n_lm * d.L_h * d.L_h
+        need = modulated_workspace(d)
+        if A is None:
+            A = torch.empty((self.n_lm, d.L_h * d.L_h), dtype=torch.complex128,
+                            device=f"cuda:{self.device}")
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        L.check(L.lib().slsht_coupling_modulated(
+            self._h, _dev_ptr(f, torch.complex128, d.L_f * d.L_f, "f"),
+            _dev_ptr(A, torch.complex128, n, "A"), _dev_ptr(work, torch.uint8, need, "work"),
+            work.numel(), _stream_handle(stream)))
+        return A
+
     def forward_windows(self, f: torch.Tensor, h: torch.Tensor, g: torch.Tensor | None = None,
                         stream=None) -> torch.Tensor:
         """One signal against W windows h[W, L_h^2]; returns g[W, *output_shape]."""
@@ -183,6 +219,25 @@ class Plan:
             _dev_ptr(h, torch.complex128, d.L_h * d.L_h, "h"),
             _dev_ptr(g, self.output_dtype, n_out, "g"),
             _dev_ptr(work, torch.uint8, need, "work"), need, _stream_handle(stream)))
+        return g
+
+    def synthesize_factored(self, A: torch.Tensor, h: torch.Tensor, g: torch.Tensor | None = None,
+                            work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """The factored synthesis alone, from a coupling A[n_lm, L_h^2]."""
+        d = self.desc
+        need = factored_workspace(d)
+        if g is None:
+            g = self.empty_output()
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        n_out = 1
+        for s in self.output_shape:
+            n_out *= s
+        L.check(L.lib().slsht_synthesize_factored(
+            self._h, _dev_ptr(A, torch.complex128, self.n_lm * d.L_h * d.L_h, "A"),
+            _dev_ptr(h, torch.complex128, d.L_h * d.L_h, "h"),
+            _dev_ptr(g, self.output_dtype, n_out, "g"),
+            _dev_ptr(work, torch.uint8, need, "work"), work.numel(), _stream_handle(stream)))
         return g
 
     def inverse(self, g: torch.Tensor, h: torch.Tensor, f_out: torch.Tensor | None = None,

@@ -466,6 +466,55 @@ int slsht_forward_factored(slsht_plan_t plan, const void* f, const void* h, void
     return SLSHT_OK;
 }
 
+int slsht_synthesize_factored(slsht_plan_t plan, const void* A, const void* h, void* g,
+                              void* work, size_t work_bytes, void* stream) {
+    if (!plan || !A || !h || !g || !work) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
+    const slsht::DevPlan& P = plan->P;
+    const int64_t need = slsht_factored_workspace(&P.d);
+    if (need < 0) return SLSHT_EINVAL;
+    if (work_bytes < (size_t)need)
+        return slsht::set_error(SLSHT_EINVAL, "workspace of %zu bytes, needs %lld", work_bytes,
+                                (long long)need);
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    hipError_t e = slsht::launch_factored(P, (const double2*)A, (const double2*)h, (double2*)g,
+                                          work, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "factored synthesis launch");
+    return SLSHT_OK;
+}
+
+int slsht_wigner_delta(int L_h, int device, void* delta, void* stream) {
+    if (!delta) return slsht::set_error(SLSHT_EINVAL, "delta is NULL");
+    if (L_h < 1 || L_h > SLSHT_MAX_LH)
+        return slsht::set_error(SLSHT_EINVAL, "L_h=%d outside [1, %d]", L_h, SLSHT_MAX_LH);
+    DeviceGuard guard(device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice(%d) failed", device);
+    hipError_t e = slsht::launch_delta_trapani(L_h, (double*)delta, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "Delta launch");
+    return SLSHT_OK;
+}
+
+int64_t slsht_modulated_workspace(const slsht_desc* desc) {
+    if (slsht::check_desc(desc) != SLSHT_OK) return -1;
+    return (int64_t)slsht::modulated_workspace_bytes(*desc);
+}
+
+int slsht_coupling_modulated(slsht_plan_t plan, const void* f, void* A, void* work,
+                             size_t work_bytes, void* stream) {
+    if (!plan || !f || !A || !work) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
+    const slsht::DevPlan& P = plan->P;
+    const size_t need = slsht::modulated_workspace_bytes(P.d);
+    if (work_bytes < need)
+        return slsht::set_error(SLSHT_EINVAL, "workspace of %zu bytes, needs %zu", work_bytes,
+                                need);
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    hipError_t e = slsht::launch_coupling_modulated(P, (const double2*)f, (double2*)A, work,
+                                                    (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "modulated coupling launch");
+    return SLSHT_OK;
+}
+
 int slsht_slepian_window(int L_h, double theta_c, double a, int device, void* h_out,
                          double* concentration) {
     if (!h_out) return slsht::set_error(SLSHT_EINVAL, "h_out is NULL");

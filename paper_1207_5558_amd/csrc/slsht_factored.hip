@@ -32,6 +32,45 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 
 }  // namespace
 
+// Delta^p_{Q,Q'} = d^p_{Q,Q'}(pi/2) in the canonical layout (0 <= Q <= p, |Q'| <= Q), by
+// the recursion of Trapani and Navaza that the paper uses (Section IV-B): one thread per
+// column (p, Q'), seeded on the edge Q = p by
+//   Delta^p_{p,Q'} = (-1)^{p-Q'} 2^{-p} sqrt(C(2p, p+Q'))
+// (Wigner's formula at beta = pi/2, where only one term survives), then down the column
+// by the first-index three-term relation of d at beta = pi/2,
+//   sqrt((p+Q)(p-Q+1)) Delta_{Q-1,Q'} = 2 Q' Delta_{Q,Q'} - sqrt((p-Q)(p+Q+1)) Delta_{Q+1,Q'},
+// down to Q = |Q'|.  O(p) work per column, O(L^3) in all.
+__global__ void delta_trapani_kernel(int L, double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L * L) return;
+    int p = (int)sqrt((double)t);
+    while (p * p > t) --p;
+    while ((p + 1) * (p + 1) <= t) ++p;
+    const int qp = t - p * p - p, aqp = qp < 0 ? -qp : qp;
+    // C(2p, p - |Q'|) by the multiplicative formula; every partial product is the
+    // integer C(p + |Q'| + i, i), exact while below 2^53
+    const int k = p - aqp;
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * (double)(p + aqp + i) / (double)i;
+    double cur = ldexp(sqrt(c), -p);
+    if ((p - qp) & 1) cur = -cur;
+    double up = 0.0;   // Delta_{Q+1,Q'}
+    double* row = out + dtab_off(p);
+    row[p * p + p + qp] = cur;
+    for (int Q = p; Q > aqp; --Q) {
+        const double nxt = (2.0 * qp * cur - sqrt((double)(p - Q) * (p + Q + 1)) * up) /
+                           sqrt((double)(p + Q) * (p - Q + 1));
+        up = cur;
+        cur = nxt;
+        row[(Q - 1) * (Q - 1) + (Q - 1) + qp] = cur;
+    }
+}
+
+hipError_t launch_delta_trapani(int L, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(delta_trapani_kernel, dim3((L * L + 127) / 128), dim3(128), 0, s, L, out);
+    return hipGetLastError();
+}
+
 // C[lm][q][q''][q'] (indices shifted by L-1); one thread per (q, q'', q'), block per lm.
 __global__ void factored_c_kernel(const double2* __restrict__ A, const double2* __restrict__ h,
                                   const double* __restrict__ delta, int L, double2* __restrict__ C) {
@@ -151,7 +190,7 @@ hipError_t launch_factored(const DevPlan& P, const double2* A, const double2* h,
     const size_t dbytes = ((size_t)dtab_row_len(L) * sizeof(double) + 255) / 256 * 256;
     double2* C = reinterpret_cast<double2*>(static_cast<char*>(work) + dbytes);
     double2* T = C + n_lm * K * K * K;
-    hipError_t e = launch_delta_table(L, delta, s);
+    hipError_t e = launch_delta_trapani(L, delta, s);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)2 * L * L * sizeof(double2) + (size_t)dtab_row_len(L) * sizeof(double);
     if (lds > 64 * 1024)

@@ -81,8 +81,14 @@ size_t device_lds_limit(int device);
 // Launchers; each returns hipSuccess or the launch error.
 hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s);
 hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipStream_t s);
+// Coupling through the modulated-signal transform (slsht_modsht.hip); work holds
+// modulated_workspace_bytes(d).
+size_t modulated_workspace_bytes(const slsht_desc& d);
+hipError_t launch_coupling_modulated(const DevPlan& P, const double2* f, double2* A, void* work,
+                                     hipStream_t s);
 // Factoring-of-rotations route on the minimal grid (slsht_factored.hip).
-hipError_t launch_delta_table(int L, double* out, hipStream_t s);
+// Delta^p = d^p(pi/2), p < L, canonical layout (dtab_row_len(L) doubles).
+hipError_t launch_delta_trapani(int L, double* out, hipStream_t s);
 size_t factored_workspace_bytes(const slsht_desc& d);
 hipError_t launch_factored(const DevPlan& P, const double2* A, const double2* h, double2* g,
                            void* work, hipStream_t s);

@@ -100,14 +100,6 @@ hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Delta^p_{Q,Q'} = d^p_{Q,Q'}(pi/2) in the canonical layout: the table kernel's row at
-// theta = 2 pi * 1 / 4.
-hipError_t launch_delta_table(int L, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(wigner_table_kernel<double>, dim3((L * L + 127) / 128, 1), dim3(128), 0, s,
-                       out, L, 4, 1, 1, dtab_row_len(L));
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------------------------------
 // K2: coupling A^p_q(l,m) = (-1)^m sqrt((2p+1)(2l+1)/(4 pi))
 //        * sum_{l'} sqrt(2l'+1) (l' p l; 0 0 0) (l' p l; m-q q -m) f_{l'}^{m-q}

@@ -120,6 +120,27 @@ def test_factored_route_workspace(lib):
         assert lib.slsht_factored_workspace(ctypes.byref(bad)) == -1
 
 
+def test_modulated_route_workspace_and_checks(lib):
+    """Workspace of the modulated-signal coupling: nodes, weights, F and two Legendre
+    tables, each padded to 256 bytes; argument checks return before any GPU work."""
+    up = lambda b: (b + 255) // 256 * 256
+    L_f, L_h, l_lo, l_hi = 8, 3, 2, 10
+    d = api.make_desc(L_f, L_h, l_lo, l_hi, 21, 11, 5)
+    n = ((L_f - 1) + (l_hi - 1) + (L_h - 1)) // 2 + 1
+    nW = l_hi * (l_hi + 1) // 2 - l_lo * (l_lo + 1) // 2
+    want = (2 * up(n * 8) + up(n * (2 * L_f - 1) * 16) + up(n * nW * 8)
+            + up(n * (L_h * (L_h + 1) // 2) * 8))
+    assert lib.slsht_modulated_workspace(ctypes.byref(d)) == want
+    assert lib.slsht_modulated_workspace(ctypes.byref(_desc(L_h=0))) == -1
+    assert lib.slsht_modulated_workspace(None) == -1
+    assert lib.slsht_coupling_modulated(None, None, None, None, 0, None) == L.SLSHT_EINVAL
+    assert lib.slsht_synthesize_factored(None, None, None, None, None, 0, None) == L.SLSHT_EINVAL
+    buf = ctypes.create_string_buffer(16)
+    for L_h in (0, 33, -1):
+        assert lib.slsht_wigner_delta(L_h, 0, buf, None) == L.SLSHT_EINVAL
+    assert lib.slsht_wigner_delta(4, 0, None, None) == L.SLSHT_EINVAL
+
+
 def test_coupling_size(lib):
     d = api.desc_for(workload("mid"))
     assert lib.slsht_coupling_size(ctypes.byref(d)) == 1280 * 64
