@@ -180,11 +180,12 @@ int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, 
  * 3-D Fourier sum of
  *   C_{q,q'',q'}(l,m) = i^{q-q'} sum_p A^p_q h_p^{q'} Delta^p_{q'',q} Delta^p_{q'',q'},
  * Delta^p = d^p(pi/2) (eq. Eq:WignerD_expansion_new), evaluated on the fly by the
- * recursion of Trapani and Navaza as the paper does.  Computed in FP64 as plain passes
- * (Delta, C, then the omega, theta and phi sums) over a caller-provided workspace.
+ * recursion of Trapani and Navaza as the paper does.  Computed in FP64 over a
+ * caller-provided workspace: Delta, the window factor of C, then per (l, m) the C
+ * slices with their omega and theta sums, then the phi sums.
  * slsht_factored_workspace(desc): bytes needed, or -1 (SLSHT_EINVAL in
  * slsht_last_error) unless desc is FULL, FP64, on that grid, over all theta rows,
- * without flags or a steerable limit, with at most 65535 (l, m).
+ * without flags or a steerable limit, with n_lm * L_h <= 2^31 - 1.
  * slsht_forward_factored: same f, h, g as slsht_forward on such a plan (coupling by
  * slsht_coupling's 3j route, then the factored synthesis); work is device memory of at
  * least work_bytes >= slsht_factored_workspace(); asynchronous.

@@ -434,7 +434,7 @@ static bool factored_eligible(const slsht_desc& d) {
     return d.output_mode == SLSHT_OUT_FULL && d.precision == SLSHT_FP64 && d.flags == 0 &&
            (d.n_az == 0 || d.n_az == d.L_h) && d.n_phi == 2 * d.L_h - 1 &&
            d.n_omega == 2 * d.L_h - 1 && d.theta_lo == 0 && theta_hi_of(d) == d.n_theta &&
-           (int64_t)d.l_hi * d.l_hi - (int64_t)d.l_lo * d.l_lo <= 65535;
+           ((int64_t)d.l_hi * d.l_hi - (int64_t)d.l_lo * d.l_lo) * d.L_h <= 0x7fffffff;
 }
 
 int64_t slsht_factored_workspace(const slsht_desc* desc) {
@@ -442,7 +442,7 @@ int64_t slsht_factored_workspace(const slsht_desc* desc) {
     if (!factored_eligible(*desc)) {
         slsht::set_error(SLSHT_EINVAL, "the factored route needs a FULL FP64 plan on the minimal "
                                        "grid n_phi = n_omega = 2 L_h - 1, all theta rows, no flags, "
-                                       "at most 65535 (l, m)");
+                                       "at most 2^31 - 1 (l, m, theta) rows");
         return -1;
     }
     return (int64_t)slsht::factored_workspace_bytes(*desc);

@@ -4,33 +4,23 @@
 //   d^p_{q,q'}(beta) = i^{q-q'} sum_{q''} Delta^p_{q'',q} Delta^p_{q'',q'} e^{-i q'' beta}
 // (eq. Eq:WignerD_expansion_new), the separated form becomes a 3-D Fourier sum
 //   g(alpha_a, beta_b, gamma_c; l, m) = sum_{q, q'', q'} C_{q,q'',q'}(l, m) e^{-i (q alpha_a + q'' beta_b + q' gamma_c)},
-//   C_{q,q'',q'}(l, m) = i^{q-q'} sum_{p >= max(|q|,|q''|,|q'|)} A^p_q(l, m) h_p^{q'} Delta^p_{q'',q} Delta^p_{q'',q'},
-// evaluated here in FP64 as four plain passes over a per-(l, m) workspace: C, then the
-// gamma, beta (b < L_h only) and alpha sums, one thread per output value.  It is the
-// paper's CPU-era design kept as a second route: the separated-form kernel K3 computes
-// the same g on this grid (and on any other) with less work.
+//   C_{q,q'',q'}(l, m) = i^{q-q'} sum_{p >= max(|q|,|q''|,|q'|)} A^p_q(l, m) h_p^{q'} Delta^p_{q'',q} Delta^p_{q'',q'}.
+// FP64, in three launches after Delta:
+//   * HD[p][q''][q'] = i^{-q'} h_p^{q'} Delta^p_{q'',q'}, the window's half of C (once per call);
+//   * one block per (l, m), looping over q: the slice C_q[q''][q'] =
+//     sum_p (i^q A^p_q Delta^p_{q'',q}) HD[p][q''][q'] in LDS, its gamma sum over q', then its
+//     beta sum over q'' for b < L_h, written as U[lm][q][b][c];
+//   * one block per (l, m, b): the alpha sum over q into g's FULL layout.
+// Each 1-D sum over k in (-L_h, L_h) with K outputs is folded: with
+// S_k^{+-} = X_k +- X_{-k}, sum_k X_k e^{-i k 2 pi j / K} = X_0 + sum_{k>0} S_k^+ cos(k 2 pi j/K)
+// - i sum_{k>0} S_k^- sin(k 2 pi j/K), and outputs j and K - j differ only in the sign of
+// the sine part; cos/sin come from a K-entry table at index k j mod K.  C is O(L_h^4)
+// per (l, m), as the paper states; the sums are direct, not FFTs (K <= 63).
 #include "slsht_device.h"
 
 #include <hip/hip_runtime.h>
 
 namespace slsht {
-
-namespace {
-
-// e^{-i k 2 pi j / K} for integer k, j: exact phase reduction, then one sincospi.
-__device__ __forceinline__ double2 phase(int k, int j, int K) {
-    int r = (int)(((int64_t)k * j) % K);
-    if (r < 0) r += K;
-    double s, c;
-    sincospi(2.0 * (double)r / (double)K, &s, &c);
-    return make_double2(c, -s);
-}
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-}  // namespace
 
 // Delta^p_{Q,Q'} = d^p_{Q,Q'}(pi/2) in the canonical layout (0 <= Q <= p, |Q'| <= Q), by
 // the recursion of Trapani and Navaza that the paper uses (Section IV-B): one thread per
@@ -71,142 +61,208 @@ hipError_t launch_delta_trapani(int L, double* out, hipStream_t s) {
     return hipGetLastError();
 }
 
-// C[lm][q][q''][q'] (indices shifted by L-1); one thread per (q, q'', q'), block per lm.
-__global__ void factored_c_kernel(const double2* __restrict__ A, const double2* __restrict__ h,
-                                  const double* __restrict__ delta, int L, double2* __restrict__ C) {
+// HD[p][q''+L-1][q'+L-1] = i^{-q'} h_p^{q'} Delta^p_{q'',q'} for p >= max(|q''|,|q'|), else 0.
+__global__ void factored_hd_kernel(const double2* __restrict__ h, const double* __restrict__ delta,
+                                   int L, double2* __restrict__ HD) {
+    const int K = 2 * L - 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * K * K) return;
+    const int p = idx / (K * K), rem = idx - p * K * K;
+    const int q2 = rem / K - (L - 1), q1 = rem % K - (L - 1);
+    const int a2 = q2 < 0 ? -q2 : q2, a1 = q1 < 0 ? -q1 : q1;
+    double2 v = make_double2(0.0, 0.0);
+    if (p >= a2 && p >= a1) {
+        int Q, Qp;
+        bool neg;
+        d_canonical(q2, q1, Q, Qp, neg);
+        double d = delta[dtab_off(p) + Q * Q + Q + Qp];
+        if (neg) d = -d;
+        const double2 hv = h[p * p + p + q1];
+        const double2 t = make_double2(hv.x * d, hv.y * d);
+        // times i^{-q'}
+        const int e = ((-q1) % 4 + 4) % 4;
+        v = e == 0 ? t : e == 1 ? make_double2(-t.y, t.x) : e == 2 ? make_double2(-t.x, -t.y)
+                                                               : make_double2(t.y, -t.x);
+    }
+    HD[idx] = v;
+}
+
+namespace {
+
+// X_0 + sum_{k=1}^{L-1} (X_k + X_{-k}) cos(2 pi k j / K) and sum_k (X_k - X_{-k}) sin(...),
+// X_k at x[k * stride] (x centred on k = 0).
+__device__ __forceinline__ void folded_sum(const double2* x, int stride, int L, int K, int j,
+                                           const double2* __restrict__ tw, double2& P, double2& S) {
+    P = x[0];
+    S = make_double2(0.0, 0.0);
+    int r = 0;
+    for (int k = 1; k < L; ++k) {
+        r += j;
+        if (r >= K) r -= K;
+        const double2 a = x[k * stride], b = x[-k * stride];
+        const double2 cs = tw[r];
+        P.x = fma(a.x + b.x, cs.x, P.x);
+        P.y = fma(a.y + b.y, cs.x, P.y);
+        S.x = fma(a.x - b.x, cs.y, S.x);
+        S.y = fma(a.y - b.y, cs.y, S.y);
+    }
+}
+
+}  // namespace
+
+// U[lm][q+L-1][b][c] = sum_{q''} e^{-i q'' beta_b} sum_{q'} C_{q,q'',q'} e^{-i q' gamma_c}, b < L.
+__global__ void __launch_bounds__(256) factored_slab_kernel(const double2* __restrict__ A,
+                                                           const double2* __restrict__ HD,
+                                                           const double* __restrict__ delta, int L,
+                                                           double2* __restrict__ U) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int K = 2 * L - 1, KKK = K * K * K;
-    double2* A_s = reinterpret_cast<double2*>(smem_raw);
-    double2* h_s = A_s + L * L;
-    double* D_s = reinterpret_cast<double*>(h_s + L * L);
-    const int lm = blockIdx.x;
-    for (int i = threadIdx.x; i < L * L; i += blockDim.x) {
-        A_s[i] = A[(int64_t)lm * L * L + i];
-        h_s[i] = h[i];
+    const int K = 2 * L - 1, KK = K * K;
+    double2* AD = reinterpret_cast<double2*>(smem_raw);      // [L][K]
+    double2* C_s = AD + L * K;                               // [K][K]  (q'', q')
+    double2* T_s = C_s + KK;                                 // [K][K]  (q'', c)
+    double2* tw = T_s + KK;                                  // [K] (cos, sin)(2 pi r / K)
+    const int64_t lm = blockIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const double2* Alm = A + lm * L * L;
+    for (int r = tid; r < K; r += nth) {
+        double sn, cs;
+        sincospi(2.0 * (double)r / (double)K, &sn, &cs);
+        tw[r] = make_double2(cs, sn);
     }
-    for (int i = threadIdx.x; i < (int)dtab_row_len(L); i += blockDim.x) D_s[i] = delta[i];
     __syncthreads();
-    double2* out = C + (int64_t)lm * KKK;
-    for (int idx = threadIdx.x; idx < KKK; idx += blockDim.x) {
-        const int q = idx / (K * K) - (L - 1);
-        const int rem = idx % (K * K);
-        const int q2 = rem / K - (L - 1), qp = rem % K - (L - 1);
-        const int aq = q < 0 ? -q : q, a2 = q2 < 0 ? -q2 : q2, ap = qp < 0 ? -qp : qp;
-        int p0 = aq > a2 ? aq : a2;
-        p0 = p0 > ap ? p0 : ap;
-        // canonical positions of Delta^p_{q'',q} and Delta^p_{q'',q'}
-        int Q1, Q1p, Q2, Q2p;
-        bool n1, n2;
-        d_canonical(q2, q, Q1, Q1p, n1);
-        d_canonical(q2, qp, Q2, Q2p, n2);
-        double sr = 0.0, si = 0.0;
-        for (int p = p0; p < L; ++p) {
-            const double d1 = D_s[dtab_off(p) + Q1 * Q1 + Q1 + Q1p];
-            const double d2 = D_s[dtab_off(p) + Q2 * Q2 + Q2 + Q2p];
-            const double2 a = A_s[p * p + p + q], hv = h_s[p * p + p + qp];
-            const double w = d1 * d2;
-            sr += (a.x * hv.x - a.y * hv.y) * w;
-            si += (a.x * hv.y + a.y * hv.x) * w;
+    double2* Ulm = U + lm * (int64_t)K * L * K;
+    for (int q = -(L - 1); q < L; ++q) {
+        const int aq = q < 0 ? -q : q;
+        // AD[p][q''] = i^q A^p_q Delta^p_{q'',q}
+        for (int i = tid; i < L * K; i += nth) {
+            const int p = i / K, q2 = i - p * K - (L - 1);
+            const int a2 = q2 < 0 ? -q2 : q2;
+            double2 v = make_double2(0.0, 0.0);
+            if (p >= aq && p >= a2) {
+                int Q, Qp;
+                bool neg;
+                d_canonical(q2, q, Q, Qp, neg);
+                double d = delta[dtab_off(p) + Q * Q + Q + Qp];
+                if (neg) d = -d;
+                const double2 a = Alm[p * p + p + q];
+                const double2 t = make_double2(a.x * d, a.y * d);
+                const int e = ((q % 4) + 4) % 4;
+                v = e == 0 ? t : e == 1 ? make_double2(-t.y, t.x) : e == 2 ? make_double2(-t.x, -t.y)
+                                                                       : make_double2(t.y, -t.x);
+            }
+            AD[i] = v;
         }
-        if (n1 != n2) { sr = -sr; si = -si; }
-        // times i^{q - q'}
-        const int e = ((q - qp) % 4 + 4) % 4;
-        double2 v = make_double2(sr, si);
-        if (e == 1) v = make_double2(-si, sr);
-        else if (e == 2) v = make_double2(-sr, -si);
-        else if (e == 3) v = make_double2(si, -sr);
-        out[idx] = v;
+        __syncthreads();
+        // C_q[q''][q'] = sum_{p >= max(|q|, |q''|, |q'|)} AD[p][q''] HD[p][q''][q']
+        for (int i = tid; i < KK; i += nth) {
+            const int q2 = i / K - (L - 1), q1 = i % K - (L - 1);
+            const int a2 = q2 < 0 ? -q2 : q2, a1 = q1 < 0 ? -q1 : q1;
+            int p0 = aq > a2 ? aq : a2;
+            p0 = p0 > a1 ? p0 : a1;
+            double sr = 0.0, si = 0.0;
+            const double2* hd = HD + i;
+            const double2* ad = AD + (q2 + L - 1);
+            for (int p = p0; p < L; ++p) {
+                const double2 x = ad[p * K], y = hd[(int64_t)p * KK];
+                sr = fma(x.x, y.x, fma(-x.y, y.y, sr));
+                si = fma(x.x, y.y, fma(x.y, y.x, si));
+            }
+            C_s[i] = make_double2(sr, si);
+        }
+        __syncthreads();
+        // gamma: T[q''][c] = sum_{q'} C_q[q''][q'] e^{-i q' gamma_c}
+        for (int i = tid; i < K * L; i += nth) {
+            const int r2 = i / L, j = i - r2 * L;
+            double2 P, S;
+            folded_sum(C_s + r2 * K + (L - 1), 1, L, K, j, tw, P, S);
+            // P - i S and, for K - j, P + i S
+            T_s[r2 * K + j] = make_double2(P.x + S.y, P.y - S.x);
+            if (j > 0) T_s[r2 * K + (K - j)] = make_double2(P.x - S.y, P.y + S.x);
+        }
+        __syncthreads();
+        // beta, b < L: U[q][b][c] = sum_{q''} T[q''][c] e^{-i q'' beta_b}
+        double2* Uq = Ulm + (int64_t)(q + L - 1) * L * K;
+        for (int i = tid; i < L * K; i += nth) {
+            const int b = i / K, c = i - b * K;
+            double2 P, S;
+            folded_sum(T_s + (L - 1) * K + c, K, L, K, b, tw, P, S);
+            Uq[i] = make_double2(P.x + S.y, P.y - S.x);
+        }
+        // the next q writes AD (read before the second barrier above) and C_s, T_s (read
+        // before the barriers that follow the next AD stage), so no barrier is needed here
     }
 }
 
-// gamma sum: T[lm][q][q''][c] = sum_{q'} C[lm][q][q''][q'] e^{-i q' gamma_c}
-__global__ void factored_gamma_kernel(const double2* __restrict__ C, int L, double2* __restrict__ T) {
+// g[lm][c][b][a] = sum_q U[lm][q][b][c] e^{-i q alpha_a}; one block per (lm, b).
+__global__ void __launch_bounds__(256) factored_alpha_kernel(const double2* __restrict__ U, int L,
+                                                            double2* __restrict__ g) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int K = 2 * L - 1;
-    const int64_t KKK = (int64_t)K * K * K;
-    const int lm = blockIdx.y;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= KKK) return;
-    const int row = idx / K, c = idx % K;
-    const double2* in = C + lm * KKK + (int64_t)row * K;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int j = 0; j < K; ++j) {
-        const double2 t = cmul(in[j], phase(j - (L - 1), c, K));
-        acc.x += t.x;
-        acc.y += t.y;
+    double2* U_s = reinterpret_cast<double2*>(smem_raw);     // [K][K] (q, c)
+    double2* tw = U_s + K * K;
+    const int64_t blk = blockIdx.x;
+    const int64_t lm = blk / L;
+    const int b = (int)(blk - lm * L);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const double2* Ulm = U + lm * (int64_t)K * L * K;
+    for (int i = tid; i < K * K; i += nth) {
+        const int q = i / K, c = i - q * K;
+        U_s[i] = Ulm[((int64_t)q * L + b) * K + c];
     }
-    T[lm * KKK + idx] = acc;
+    for (int r = tid; r < K; r += nth) {
+        double sn, cs;
+        sincospi(2.0 * (double)r / (double)K, &sn, &cs);
+        tw[r] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    double2* glm = g + lm * (int64_t)K * L * K;
+    for (int i = tid; i < K * L; i += nth) {
+        const int c = i / L, j = i - c * L;
+        double2 P, S;
+        folded_sum(U_s + (L - 1) * K + c, K, L, K, j, tw, P, S);
+        double2* row = glm + ((int64_t)c * L + b) * K;
+        row[j] = make_double2(P.x + S.y, P.y - S.x);
+        if (j > 0) row[K - j] = make_double2(P.x - S.y, P.y + S.x);
+    }
 }
 
-// beta sum, b < L: U[lm][q][b][c] = sum_{q''} T[lm][q][q''][c] e^{-i q'' beta_b}
-__global__ void factored_beta_kernel(const double2* __restrict__ T, int L, double2* __restrict__ U) {
-    const int K = 2 * L - 1;
-    const int64_t KKK = (int64_t)K * K * K, KLK = (int64_t)K * L * K;
-    const int lm = blockIdx.y;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= KLK) return;
-    const int q = idx / (L * K), rem = idx % (L * K);
-    const int b = rem / K, c = rem % K;
-    const double2* in = T + lm * KKK + (int64_t)q * K * K + c;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int j = 0; j < K; ++j) {
-        const double2 t = cmul(in[(int64_t)j * K], phase(j - (L - 1), b, K));
-        acc.x += t.x;
-        acc.y += t.y;
-    }
-    U[lm * KLK + idx] = acc;
-}
-
-// alpha sum into the FULL layout: g[lm][c][b][a] = sum_q U[lm][q][b][c] e^{-i q alpha_a}
-__global__ void factored_alpha_kernel(const double2* __restrict__ U, int L, double2* __restrict__ g) {
-    const int K = 2 * L - 1;
-    const int64_t KLK = (int64_t)K * L * K;
-    const int lm = blockIdx.y;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= KLK) return;
-    const int c = idx / (L * K), rem = idx % (L * K);
-    const int b = rem / K, a = rem % K;
-    const double2* in = U + lm * KLK + (int64_t)b * K + c;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int j = 0; j < K; ++j) {
-        const double2 t = cmul(in[(int64_t)j * L * K], phase(j - (L - 1), a, K));
-        acc.x += t.x;
-        acc.y += t.y;
-    }
-    g[lm * KLK + idx] = acc;
-}
+namespace {
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
 
 size_t factored_workspace_bytes(const slsht_desc& d) {
-    const int64_t K = 2 * d.L_h - 1;
+    const int64_t L = d.L_h, K = 2 * L - 1;
     const int64_t n_lm = (int64_t)d.l_hi * d.l_hi - (int64_t)d.l_lo * d.l_lo;
-    const size_t delta = ((size_t)dtab_row_len(d.L_h) * sizeof(double) + 255) / 256 * 256;
-    return delta + (size_t)2 * n_lm * K * K * K * sizeof(double2);
+    return up256((size_t)dtab_row_len(d.L_h) * sizeof(double)) +
+           up256((size_t)L * K * K * sizeof(double2)) + (size_t)n_lm * K * L * K * sizeof(double2);
 }
 
 hipError_t launch_factored(const DevPlan& P, const double2* A, const double2* h, double2* g,
                            void* work, hipStream_t s) {
     const int L = P.d.L_h, K = 2 * L - 1;
     const int64_t n_lm = P.n_lm;
-    double* delta = static_cast<double*>(work);
-    const size_t dbytes = ((size_t)dtab_row_len(L) * sizeof(double) + 255) / 256 * 256;
-    double2* C = reinterpret_cast<double2*>(static_cast<char*>(work) + dbytes);
-    double2* T = C + n_lm * K * K * K;
+    char* base = static_cast<char*>(work);
+    double* delta = reinterpret_cast<double*>(base);
+    const size_t dbytes = up256((size_t)dtab_row_len(L) * sizeof(double));
+    double2* HD = reinterpret_cast<double2*>(base + dbytes);
+    double2* U = reinterpret_cast<double2*>(base + dbytes + up256((size_t)L * K * K * sizeof(double2)));
     hipError_t e = launch_delta_trapani(L, delta, s);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)2 * L * L * sizeof(double2) + (size_t)dtab_row_len(L) * sizeof(double);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)factored_c_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(factored_c_kernel, dim3((unsigned)n_lm), dim3(256), lds, s, A, h, delta, L, C);
+    hipLaunchKernelGGL(factored_hd_kernel, dim3((L * K * K + 255) / 256), dim3(256), 0, s, h, delta,
+                       L, HD);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t KKK = (int64_t)K * K * K, KLK = (int64_t)K * L * K;
-    hipLaunchKernelGGL(factored_gamma_kernel, dim3((unsigned)((KKK + 255) / 256), (unsigned)n_lm),
-                       dim3(256), 0, s, C, L, T);
+    const size_t lds1 = (size_t)(L * K + 2 * K * K + K) * sizeof(double2);   // <= 160 KiB at L = 32
+    if (lds1 > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)factored_slab_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
+    hipLaunchKernelGGL(factored_slab_kernel, dim3((unsigned)n_lm), dim3(256), lds1, s, A, HD, delta,
+                       L, U);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(factored_beta_kernel, dim3((unsigned)((KLK + 255) / 256), (unsigned)n_lm),
-                       dim3(256), 0, s, T, L, C);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(factored_alpha_kernel, dim3((unsigned)((KLK + 255) / 256), (unsigned)n_lm),
-                       dim3(256), 0, s, C, L, g);
+    const size_t lds2 = (size_t)(K * K + K) * sizeof(double2);
+    if (lds2 > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)factored_alpha_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+    hipLaunchKernelGGL(factored_alpha_kernel, dim3((unsigned)(n_lm * L)), dim3(256), lds2, s, U, L, g);
     return hipGetLastError();
 }
 

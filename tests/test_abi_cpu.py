@@ -110,9 +110,10 @@ def test_slepian_window_argument_checks(lib):
 def test_factored_route_workspace(lib):
     """Host-only eligibility and size of the factoring-of-rotations workspace."""
     d = api.make_desc(8, 3, 0, 10, 5, 3, 5)                      # minimal grid, K = 5
-    n_lm, K, row = 100, 5, 3 * 4 * 7 // 6
-    delta = (row * 8 + 255) // 256 * 256
-    assert lib.slsht_factored_workspace(ctypes.byref(d)) == delta + 2 * n_lm * K ** 3 * 16
+    n_lm, L_h, K, row = 100, 3, 5, 3 * 4 * 7 // 6
+    up = lambda b: (b + 255) // 256 * 256
+    want = up(row * 8) + up(L_h * K * K * 16) + n_lm * K * L_h * K * 16
+    assert lib.slsht_factored_workspace(ctypes.byref(d)) == want
     for bad in (api.make_desc(8, 3, 0, 10, 21, 11, 5),          # not the minimal grid
                 api.make_desc(8, 3, 0, 10, 5, 3, 5, precision="fp32"),
                 api.make_desc(8, 3, 0, 10, 5, 3, 5, real_pair=True),
