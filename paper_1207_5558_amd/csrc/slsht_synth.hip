@@ -164,11 +164,14 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* S_s = reinterpret_cast<V*>(smem_raw);
     const int L = a.L, K = a.K;
-    const int PMS = 2 * LH + 1;                  // complex stride of one P|M row
+    // P|M row: P_0..P_{PW-1} M_0..M_{PW-1}; the VALU phi stage reads LH entries, the MFMA
+    // stage the k-steps that cover L
+    const int PW = LH <= 8 ? LH : (L + 3) / 4 * 4;
+    const int PMS = 2 * PW + 1;                  // complex stride of one P|M row
     V* X_s = S_s + a.tb * K * K;
     V* A_s = X_s;
-    V* h_s = X_s + LH * LH;
-    V* PM_s = X_s;                               // [c*tb + t][P_0..P_{LH-1} M_0..M_{LH-1}]
+    V* h_s = X_s + L * L;
+    V* PM_s = X_s;                               // [c*tb + t][P_0..P_{PW-1} M_0..M_{PW-1}]
     V* TW_s = X_s + a.xsize;                     // [L-1][ncp] omega twiddles
 
     const int item = blockIdx.x / a.n_tiles;
@@ -234,11 +237,11 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
             if (c < 0) break;
             const V Up = side == 0 ? vadd(Xp, Yp) : vsub(Xp, Yp);
             V* P = PM_s + (c * tb + t) * PMS;
-            V* M = P + LH;
+            V* M = P + PW;
             if (qa == 0) {
                 P[0] = Up;
                 M[0] = vmk<V>(0, 0);
-                for (int k = L; k < LH; ++k) { P[k] = vmk<V>(0, 0); M[k] = vmk<V>(0, 0); }
+                for (int k = L; k < PW; ++k) { P[k] = vmk<V>(0, 0); M[k] = vmk<V>(0, 0); }
             } else {
                 const V Um = side == 0 ? vadd(Xm, Ym) : vsub(Xm, Ym);
                 P[qa] = vadd(Up, Um);
@@ -358,7 +361,7 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
             for (int kk = 0; kk < KQ; ++kk) {
                 const int k = 4 * kk + lj;
                 pa[kk] = (kk < kq && ra < nrows) ? prow[2 * k] : T(0);
-                ma[kk] = (kk < kq && ra < nrows) ? prow[2 * (LH + k)] : T(0);
+                ma[kk] = (kk < kq && ra < nrows) ? prow[2 * (PW + k)] : T(0);
             }
             // w[x][e]: x = 16-slot tile of the unit, e = (row h, value): Re/Im of C+S, C-S
             T w[4][8];
@@ -420,8 +423,9 @@ static int lh_bucket(int L) { return L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : 
 
 static size_t synth_xsize(const DevPlan& P, int tb) {
     const int LH = lh_bucket(P.d.L_h);
+    const int PW = LH <= 8 ? LH : (P.d.L_h + 3) / 4 * 4;
     const size_t rows = ((size_t)tb * P.d.n_omega + 7) / 8 * 8;
-    return std::max((size_t)2 * LH * LH, rows * (2 * LH + 1));
+    return std::max((size_t)2 * P.d.L_h * P.d.L_h, rows * (2 * PW + 1));
 }
 
 static size_t synth_lds_bytes(const DevPlan& P, int tb) {
