@@ -151,6 +151,18 @@ int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void
  * windows, Section IV-B).  Asynchronous on `stream`. */
 int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream);
 
+/* Several forward transforms in few launches (continuous batching, Section IV-B's
+ * separated form for each): the couplings of all n plans, then one synthesis grid per
+ * group of up to 16 FULL plans that share a synthesis kernel (same precision, band-limit
+ * bucket and phi-slot class), its blocks split between the transforms by a tile list;
+ * ENERGY plans get their own launch.  Results equal n separate slsht_forward calls.
+ *   plans: n distinct plans on one device (each plan's coupling scratch is used);
+ *   f[i], h[i], g[i]: device pointers as for slsht_forward on plans[i].
+ * n >= 1 (SLSHT_EINVAL otherwise, also for a repeated plan or a NULL entry).
+ * Asynchronous on `stream`. */
+int slsht_forward_batch(int n, const slsht_plan_t* plans, const void* const* f,
+                        const void* const* h, void* const* g, void* stream);
+
 /* Forward transform of one signal against several windows (remark on multiple
  * windows, Section IV-B): the coupling of f is computed once and shared; each
  * window then costs one synthesis.  Same plan rules as slsht_forward.

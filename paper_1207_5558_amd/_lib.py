@@ -55,6 +55,7 @@ _SIGNATURES = {
     "slsht_forward_windows": ([_P, _P, _P, ctypes.c_int, _P, _P], ctypes.c_int),
     "slsht_factored_workspace": ([ctypes.POINTER(Desc)], ctypes.c_int64),
     "slsht_forward_factored": ([_P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "slsht_forward_batch": ([ctypes.c_int, _P, _P, _P, _P, _P], ctypes.c_int),
     "slsht_synthesize_factored": ([_P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "slsht_wigner_delta": ([ctypes.c_int, ctypes.c_int, _P, _P], ctypes.c_int),
     "slsht_modulated_workspace": ([ctypes.POINTER(Desc)], ctypes.c_int64),

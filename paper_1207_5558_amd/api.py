@@ -68,6 +68,30 @@ def wigner_delta(L_h: int, device: int = 0, stream=None):
     return out
 
 
+def forward_batch(plans, fs, hs, gs=None, stream=None):
+    """Forward transforms of several distinct plans in few launches (slsht_forward_batch);
+    returns the outputs (allocated if gs is None)."""
+    n = len(plans)
+    if not (len(fs) == len(hs) == n) or (gs is not None and len(gs) != n):
+        raise ValueError("plans, fs, hs (and gs) must have equal lengths")
+    if gs is None:
+        gs = [p.empty_output() for p in plans]
+    def n_out(p):
+        k = 1
+        for s in p.output_shape:
+            k *= s
+        return k
+    P = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+    F = (ctypes.c_void_p * n)(*[_dev_ptr(f, torch.complex128, p.desc.L_f ** 2, "f").value
+                                for p, f in zip(plans, fs)])
+    H = (ctypes.c_void_p * n)(*[_dev_ptr(h, torch.complex128, p.desc.L_h ** 2, "h").value
+                                for p, h in zip(plans, hs)])
+    G = (ctypes.c_void_p * n)(*[_dev_ptr(g, p.output_dtype, n_out(p), "g").value
+                                for p, g in zip(plans, gs)])
+    L.check(L.lib().slsht_forward_batch(n, P, F, H, G, _stream_handle(stream)))
+    return gs
+
+
 def validate(desc: L.Desc) -> None:
     L.check(L.lib().slsht_validate(ctypes.byref(desc)))
 

@@ -408,6 +408,58 @@ int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void
     return SLSHT_OK;
 }
 
+int slsht_forward_batch(int n, const slsht_plan_t* plans, const void* const* f,
+                        const void* const* h, void* const* g, void* stream) {
+    if (n < 1) return slsht::set_error(SLSHT_EINVAL, "n=%d < 1", n);
+    if (!plans || !f || !h || !g) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i] || !f[i] || !h[i] || !g[i])
+            return slsht::set_error(SLSHT_EINVAL, "NULL entry %d", i);
+        if (plans[i]->device != plans[0]->device)
+            return slsht::set_error(SLSHT_EINVAL, "plan %d is on device %d, plan 0 on %d", i,
+                                    plans[i]->device, plans[0]->device);
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i])
+                return slsht::set_error(SLSHT_EINVAL, "plan %d repeats plan %d (one coupling "
+                                        "scratch per plan)", i, j);
+    }
+    DeviceGuard guard(plans[0]->device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = slsht::launch_coupling(plans[i]->P, (const double2*)f[i], plans[i]->P.A, s);
+    // FULL transforms grouped by synthesis kernel, up to kSynthBatchMax per grid
+    std::vector<char> done(n, 0);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        if (done[i]) continue;
+        const slsht::DevPlan& Pi = plans[i]->P;
+        if (Pi.d.output_mode != SLSHT_OUT_FULL) {
+            e = slsht::launch_energy(Pi, Pi.A, (const double2*)h[i], (float*)g[i], s);
+            done[i] = 1;
+            continue;
+        }
+        const void* key = slsht::synthesis_kernel_key(Pi);
+        std::vector<const slsht::DevPlan*> P;
+        std::vector<const double2*> A, H;
+        std::vector<void*> G;
+        for (int j = i; j < n && (int)P.size() < slsht::kSynthBatchMax; ++j) {
+            const slsht::DevPlan& Pj = plans[j]->P;
+            if (done[j] || Pj.d.output_mode != SLSHT_OUT_FULL ||
+                slsht::synthesis_kernel_key(Pj) != key || Pj.block != Pi.block)
+                continue;
+            P.push_back(&Pj);
+            A.push_back(Pj.A);
+            H.push_back((const double2*)h[j]);
+            G.push_back(g[j]);
+            done[j] = 1;
+        }
+        e = slsht::launch_synthesis_batch(P.data(), A.data(), H.data(), G.data(), (int)P.size(), s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return SLSHT_OK;
+}
+
 int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n_windows,
                           void* g, void* stream) {
     if (!plan || !f || !h || !g) return slsht::set_error(SLSHT_EINVAL, "NULL argument");

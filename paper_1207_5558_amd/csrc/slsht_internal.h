@@ -96,6 +96,12 @@ hipError_t launch_factored(const DevPlan& P, const double2* A, const double2* h,
 int slepian_window(int L, double theta_c, double a, double2* h_out, double* concentration);
 hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
                             hipStream_t s);
+// Up to kSynthBatchMax FULL transforms in one grid; they must share one synthesis
+// kernel (equal synthesis_kernel_key) and block size.
+constexpr int kSynthBatchMax = 16;
+const void* synthesis_kernel_key(const DevPlan& P);
+hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const* A,
+                                  const double2* const* h, void* const* g, int n, hipStream_t s);
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
                          hipStream_t s);
 hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,

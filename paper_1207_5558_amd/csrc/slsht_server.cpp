@@ -3,10 +3,11 @@
 // Callers submit descriptors with host coefficient arrays and get a ticket back at
 // once.  A worker thread admits queued requests in arrival order whenever their
 // footprint (output + inputs + coupling scratch) fits the server's HBM arena,
-// letting smaller later requests pass a head that does not fit yet; it enqueues
-// each admitted request's kernels on one of the server's streams, so transforms of
-// different requests run concurrently, and retires requests as their completion
-// events fire.  Device tables (Wigner-d, twiddles) are cached by the fields they
+// letting smaller later requests pass a head that does not fit yet.  The requests
+// admitted in one round are launched together: FULL transforms that share a synthesis
+// kernel go into one grid (a tile list over up to kSynthBatchMax requests), each group
+// on the next of the server's streams, so groups of different rounds also overlap on
+// the device; requests retire as their completion events fire.  Device tables (Wigner-d, twiddles) are cached by the fields they
 // depend on and stay resident across requests.
 #include <hip/hip_runtime.h>
 
@@ -109,7 +110,8 @@ struct slsht_server_s {
             it = it->second.use_count() == 1 ? tables.erase(it) : std::next(it);
     }
 
-    int launch(Request& r) {
+    // Host side of a launch: device tables (cached) and the request's plan view.
+    int prepare(Request& r) {
         const std::string key = slsht::tables_key(r.d);
         auto it = tables.find(key);
         if (it == tables.end()) {
@@ -119,28 +121,102 @@ struct slsht_server_s {
             if (rc) return rc;
             it = tables.emplace(key, T).first;
         }
-        int rc = slsht::make_view(r.d, it->second, lds_limit, r.P);
-        if (rc) return rc;
+        return slsht::make_view(r.d, it->second, lds_limit, r.P);
+    }
+
+    struct DevPtrs {
+        double2 *f, *h, *A;
+        void* g;
+    };
+    DevPtrs ptrs(Request& r) {
         char* in = base + r.in_off;
-        double2* f_dev = reinterpret_cast<double2*>(in);
-        double2* h_dev = reinterpret_cast<double2*>(in + al(r.f.size() * sizeof(double2)));
-        double2* A_dev = reinterpret_cast<double2*>(in + al(r.f.size() * sizeof(double2)) +
-                                                    al(r.h.size() * sizeof(double2)));
+        DevPtrs p;
+        p.f = reinterpret_cast<double2*>(in);
+        p.h = reinterpret_cast<double2*>(in + al(r.f.size() * sizeof(double2)));
+        p.A = reinterpret_cast<double2*>(in + al(r.f.size() * sizeof(double2)) +
+                                         al(r.h.size() * sizeof(double2)));
+        p.g = base + r.out_off;
+        return p;
+    }
+
+    // Enqueues one group on one stream: inputs, couplings, then one synthesis grid for all
+    // of its transforms (FULL requests sharing a kernel) or the energy kernel (a group of
+    // one); each request gets its own completion event.
+    hipError_t launch_group(const std::vector<Request*>& grp) {
         hipStream_t s = streams[next_stream++ % streams.size()];
-        hipError_t e = hipMemcpyAsync(f_dev, r.f.data(), r.f.size() * sizeof(double2),
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h_dev, r.h.data(), r.h.size() * sizeof(double2),
-                               hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = slsht::enqueue_forward(r.P, f_dev, h_dev, base + r.out_off, A_dev, s);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(r.done, s);
-        if (e != hipSuccess)
-            return slsht::set_error(SLSHT_EDEVICE, "enqueue: %s", hipGetErrorString(e));
-        return SLSHT_OK;
+        hipError_t e = hipSuccess;
+        std::vector<const slsht::DevPlan*> P;
+        std::vector<const double2*> A, H;
+        std::vector<void*> G;
+        for (Request* r : grp) {
+            const DevPtrs d = ptrs(*r);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d.f, r->f.data(), r->f.size() * sizeof(double2),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d.h, r->h.data(), r->h.size() * sizeof(double2),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = slsht::launch_coupling(r->P, d.f, d.A, s);
+            P.push_back(&r->P);
+            A.push_back(d.A);
+            H.push_back(d.h);
+            G.push_back(d.g);
+        }
+        if (e == hipSuccess) {
+            if (grp[0]->d.output_mode != SLSHT_OUT_FULL)
+                e = slsht::launch_energy(*P[0], A[0], H[0], (float*)G[0], s);
+            else if (grp.size() == 1)
+                e = slsht::launch_synthesis(*P[0], A[0], H[0], G[0], s);
+            else
+                e = slsht::launch_synthesis_batch(P.data(), A.data(), H.data(), G.data(),
+                                                  (int)grp.size(), s);
+        }
+        for (Request* r : grp) {
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(r->done, s);
+        }
+        // on failure the group's arena blocks are released: let what was enqueued drain first
+        if (e != hipSuccess) (void)hipStreamSynchronize(s);
+        return e;
+    }
+
+    // Launches the requests admitted in one scheduling round: FULL requests that share a
+    // synthesis kernel go into common grids of up to kSynthBatchMax transforms.
+    void launch_round(std::vector<Request*>& fresh) {
+        std::vector<char> used(fresh.size(), 0);
+        for (size_t i = 0; i < fresh.size(); ++i) {
+            if (used[i]) continue;
+            std::vector<Request*> grp{fresh[i]};
+            used[i] = 1;
+            if (fresh[i]->d.output_mode == SLSHT_OUT_FULL) {
+                const void* key = slsht::synthesis_kernel_key(fresh[i]->P);
+                for (size_t j = i + 1; j < fresh.size() && (int)grp.size() < slsht::kSynthBatchMax; ++j) {
+                    Request& rj = *fresh[j];
+                    if (used[j] || rj.d.output_mode != SLSHT_OUT_FULL ||
+                        slsht::synthesis_kernel_key(rj.P) != key || rj.P.block != fresh[i]->P.block)
+                        continue;
+                    grp.push_back(&rj);
+                    used[j] = 1;
+                }
+            }
+            const hipError_t e = launch_group(grp);
+            for (Request* r : grp) {
+                if (e != hipSuccess) {
+                    r->state = SLSHT_REQ_FAILED;
+                    r->err = slsht::set_error(SLSHT_EDEVICE, "enqueue: %s", hipGetErrorString(e));
+                    r->t_done = now();
+                    free_blocks(*r, true);
+                } else {
+                    r->state = SLSHT_REQ_RUNNING;
+                    running.push_back(r->ticket);
+                }
+            }
+            done_cv.notify_all();
+        }
     }
 
     void admit() {
+        std::vector<Request*> fresh;
         for (auto qi = queue.begin(); qi != queue.end();) {
             Request& r = *reqs[*qi];
             const size_t out = arena.alloc(r.out_bytes);
@@ -157,7 +233,7 @@ struct slsht_server_s {
             r.out_off = out;
             r.in_off = in;
             r.t_start = now();
-            const int rc = launch(r);
+            const int rc = prepare(r);
             if (rc) {
                 r.state = SLSHT_REQ_FAILED;
                 r.err = rc;
@@ -165,11 +241,11 @@ struct slsht_server_s {
                 free_blocks(r, true);
                 done_cv.notify_all();
             } else {
-                r.state = SLSHT_REQ_RUNNING;
-                running.push_back(r.ticket);
+                fresh.push_back(&r);
             }
             qi = queue.erase(qi);
         }
+        if (!fresh.empty()) launch_round(fresh);
     }
 
     void loop() {

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 namespace slsht {
 
@@ -41,6 +42,12 @@ struct SynthArgs {
     int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp, l_lo, real_pair;
     int N;        // azimuthal band-limit of the window (|q'| < N)
     int xsize;    // elements of the A/h | P/M union region in LDS
+};
+
+struct SynthBatch {
+    SynthArgs r[kSynthBatchMax];
+    int first[kSynthBatchMax + 1];
+    int n;
 };
 
 // Synthesis item -> output slot lm, degree l, order m and the slot of order -m that is
@@ -155,8 +162,9 @@ __device__ __forceinline__ void load_phi_b(const typename VecOf<T>::type* __rest
     }
 }
 
+// One block of one transform: block `bid` of the grid that a.n_items x a.n_tiles blocks form.
 template <typename T, int LH, int NS>
-__global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
+__device__ __forceinline__ void synth_block(const SynthArgs& a, const int bid) {
     using V = typename VecOf<T>::type;
     using MF = MfmaOf<T>;
     using Acc = typename MF::acc;
@@ -174,8 +182,8 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     V* PM_s = X_s;                               // [c*tb + t][P_0..P_{PW-1} M_0..M_{PW-1}]
     V* TW_s = X_s + a.xsize;                     // [L-1][ncp] omega twiddles
 
-    const int item = blockIdx.x / a.n_tiles;
-    const int tile = blockIdx.x - item * a.n_tiles;
+    const int item = bid / a.n_tiles;
+    const int tile = bid - item * a.n_tiles;
     const Item it = item_decode(item, a.l_lo, a.real_pair);
     const int t0 = tile * a.tb;
     const int tb = min(a.tb, a.n_theta_out - t0);
@@ -419,6 +427,21 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     }
 }
 
+template <typename T, int LH, int NS>
+__global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
+    synth_block<T, LH, NS>(a, (int)blockIdx.x);
+}
+
+// Several transforms that share one kernel instance in one grid (a tile list across
+// requests): transform r owns blocks [first[r], first[r+1]).  The per-transform arguments
+// travel in the kernel-argument block, so a launch needs no device allocation or copy.
+template <typename T, int LH, int NS>
+__global__ void __launch_bounds__(256) synth_batch_kernel(const SynthBatch b) {
+    int r = 0;
+    while (r + 1 < b.n && (int)blockIdx.x >= b.first[r + 1]) ++r;
+    synth_block<T, LH, NS>(b.r[r], (int)blockIdx.x - b.first[r]);
+}
+
 static int lh_bucket(int L) { return L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : 32)); }
 
 static size_t synth_xsize(const DevPlan& P, int tb) {
@@ -443,35 +466,42 @@ static int ns_max(bool f64, int LH) {
     return 4;
 }
 
+template <typename T, int LH, int NS>
+static const void* synth_pick(bool batch) {
+    return batch ? (const void*)synth_batch_kernel<T, LH, NS> : (const void*)synth_full_kernel<T, LH, NS>;
+}
+
 template <typename T, int LH>
-static const void* synth_fn_t(int nslot) {
+static const void* synth_fn_t(int nslot, bool batch) {
     if constexpr (LH >= 16) {
-        return (const void*)synth_full_kernel<T, LH, 1>;
+        return synth_pick<T, LH, 1>(batch);
     } else {
         const int ns = std::min((nslot + 63) / 64, ns_max(sizeof(T) == 8, LH));
         if constexpr (sizeof(T) == 8 && LH == 8) {
-            return ns <= 1 ? (const void*)synth_full_kernel<T, LH, 1>
-                 : ns == 2 ? (const void*)synth_full_kernel<T, LH, 2>
-                           : (const void*)synth_full_kernel<T, LH, 3>;
+            return ns <= 1 ? synth_pick<T, LH, 1>(batch)
+                 : ns == 2 ? synth_pick<T, LH, 2>(batch)
+                           : synth_pick<T, LH, 3>(batch);
         } else {
-            return ns <= 1 ? (const void*)synth_full_kernel<T, LH, 1>
-                 : ns == 2 ? (const void*)synth_full_kernel<T, LH, 2>
-                 : ns == 3 ? (const void*)synth_full_kernel<T, LH, 3>
-                           : (const void*)synth_full_kernel<T, LH, 4>;
+            return ns <= 1 ? synth_pick<T, LH, 1>(batch)
+                 : ns == 2 ? synth_pick<T, LH, 2>(batch)
+                 : ns == 3 ? synth_pick<T, LH, 3>(batch)
+                           : synth_pick<T, LH, 4>(batch);
         }
     }
 }
 
-static const void* synth_fn(const DevPlan& P) {
+static const void* synth_fn(const DevPlan& P, bool batch = false) {
     const bool f64 = P.d.precision == SLSHT_FP64;
     const int ns = P.nslot_phi;
     switch (lh_bucket(P.d.L_h)) {
-        case 4: return f64 ? synth_fn_t<double, 4>(ns) : synth_fn_t<float, 4>(ns);
-        case 8: return f64 ? synth_fn_t<double, 8>(ns) : synth_fn_t<float, 8>(ns);
-        case 16: return f64 ? synth_fn_t<double, 16>(ns) : synth_fn_t<float, 16>(ns);
-        default: return f64 ? synth_fn_t<double, 32>(ns) : synth_fn_t<float, 32>(ns);
+        case 4: return f64 ? synth_fn_t<double, 4>(ns, batch) : synth_fn_t<float, 4>(ns, batch);
+        case 8: return f64 ? synth_fn_t<double, 8>(ns, batch) : synth_fn_t<float, 8>(ns, batch);
+        case 16: return f64 ? synth_fn_t<double, 16>(ns, batch) : synth_fn_t<float, 16>(ns, batch);
+        default: return f64 ? synth_fn_t<double, 32>(ns, batch) : synth_fn_t<float, 32>(ns, batch);
     }
 }
+
+const void* synthesis_kernel_key(const DevPlan& P) { return synth_fn(P); }
 
 // Theta rows per block: stages 1-2 run between barriers with no stores in flight, so
 // the store stream is kept busy by other resident blocks.  The tile is the largest one
@@ -498,8 +528,7 @@ bool choose_synthesis_shape(DevPlan& P, size_t lds_limit) {
     return true;
 }
 
-hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
-                            hipStream_t s) {
+static SynthArgs synth_args(const DevPlan& P, const double2* A, const double2* h, void* g) {
     SynthArgs a;
     a.A = A;
     a.h = h;
@@ -521,10 +550,41 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
     a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     a.xsize = (int)synth_xsize(P, P.tb);
     a.N = n_az_of(P.d);
+    return a;
+}
+
+hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
+                            hipStream_t s) {
+    SynthArgs a = synth_args(P, A, h, g);
     const int64_t nblk = (int64_t)P.n_items * a.n_tiles;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;   // grid.x limit
     void* args[] = {&a};
     return hipLaunchKernel(synth_fn(P), dim3((unsigned)nblk), dim3(P.block), args, P.lds_bytes, s);
+}
+
+hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const* A,
+                                  const double2* const* h, void* const* g, int n, hipStream_t s) {
+    if (n < 1 || n > kSynthBatchMax) return hipErrorInvalidValue;
+    const void* fn = synth_fn(*P[0], true);
+    SynthBatch b;
+    std::memset(&b, 0, sizeof(b));
+    b.n = n;
+    int64_t nblk = 0;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+        if (synth_fn(*P[i], true) != fn || P[i]->block != P[0]->block)
+            return hipErrorInvalidValue;                               // one kernel per launch
+        b.r[i] = synth_args(*P[i], A[i], h[i], g[i]);
+        b.first[i] = (int)nblk;
+        nblk += (int64_t)P[i]->n_items * b.r[i].n_tiles;
+        if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
+        lds = std::max(lds, P[i]->lds_bytes);
+    }
+    b.first[n] = (int)nblk;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    void* args[] = {&b};
+    return hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(P[0]->block), args, lds, s);
 }
 
 }  // namespace slsht

@@ -142,6 +142,14 @@ def test_modulated_route_workspace_and_checks(lib):
     assert lib.slsht_wigner_delta(4, 0, None, None) == L.SLSHT_EINVAL
 
 
+def test_forward_batch_argument_checks(lib):
+    """Rejected on the host before any GPU work."""
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.slsht_forward_batch(0, arr, arr, arr, arr, None) == L.SLSHT_EINVAL
+    assert lib.slsht_forward_batch(1, None, arr, arr, arr, None) == L.SLSHT_EINVAL
+    assert lib.slsht_forward_batch(1, arr, arr, arr, arr, None) == L.SLSHT_EINVAL
+
+
 def test_coupling_size(lib):
     d = api.desc_for(workload("mid"))
     assert lib.slsht_coupling_size(ctypes.byref(d)) == 1280 * 64

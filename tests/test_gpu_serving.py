@@ -44,12 +44,17 @@ def _alone(req, f, h, output="full"):
     return plan.forward(dev(f), dev(h)).cpu().numpy().ravel()
 
 
-def test_mix_equals_alone_bitwise():
-    announce("serving mix vs alone")
+@pytest.mark.parametrize("roomy", [False, True])
+def test_mix_equals_alone_bitwise(roomy):
+    """roomy=False: a budget of three of the largest outputs forces queueing; roomy=True:
+    everything is admitted in the first round, so requests that share a synthesis kernel
+    run in common grids."""
+    announce(f"serving mix vs alone (roomy={roomy})")
     reqs = _mix(24)
     inputs = [r.inputs() for r in reqs]
     biggest = max(api.footprint(request_desc(r))[1] for r in reqs)
-    srv = Server(hbm_budget=3 * biggest + (64 << 20), n_streams=4)
+    budget = (4 << 30) if roomy else 3 * biggest + (64 << 20)
+    srv = Server(hbm_budget=budget, n_streams=4)
     tickets = [srv.submit(request_desc(r), f, h) for r, (f, h) in zip(reqs, inputs)]
     u, b, q, running = srv.stats()
     assert u <= b
