@@ -382,6 +382,31 @@ def main():
             f"p99 {np.percentile(per, 99):.3f}), coupling {cpl.mean():.4f} ms, "
             f"{samples / (per.mean() * 1e-3):.3e} samples/s")
 
+    # the practical write ceiling on this device: hipMemsetAsync of a buffer the size of
+    # the FP64 output, timed like the forward on the same stream
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemsetAsync.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p]
+    hip.hipMemsetAsync.restype = ctypes.c_int
+    g64 = torch.empty_like(outputs["fp64"])
+    nbytes = g64.numel() * g64.element_size()
+    stream = torch.cuda.current_stream()
+    fill = lambda: hip.hipMemsetAsync(ctypes.c_void_p(g64.data_ptr()), 0, nbytes,
+                                      ctypes.c_void_p(stream.cuda_stream))
+    if fill() != 0:
+        raise RuntimeError("hipMemsetAsync failed")
+    torch.cuda.synchronize()
+    fs_, fe_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fs_.record()
+    for _ in range(5):
+        fill()
+    fe_.record()
+    torch.cuda.synchronize()
+    fill_gbs = nbytes * 5 / (fs_.elapsed_time(fe_) * 1e-3) / 1e9
+    log(f"hipMemsetAsync of a buffer the size of the FP64 output: {fill_gbs:.0f} GB/s")
+    del g64
+    torch.cuda.empty_cache()
+
     r = results["fp64"]
     ms = float(r["per"].mean())
     kern_ms = float(r["per"].mean() - r["cpl"].mean())
@@ -417,6 +442,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel_ms": kern_ms,
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     "measured_fill_GBps": fill_gbs, "frac_of_measured_fill": achieved / fill_gbs,
                      "kernel_source_sha256_16": digest},
     }
     r32 = results["fp32"]
