@@ -110,3 +110,26 @@ def test_window_is_real_unit_and_concentrated():
         v = rng.standard_normal(L_h * L_h) + 1j * rng.standard_normal(L_h * L_h)
         v /= np.linalg.norm(v)
         assert np.vdot(v, D @ v).real < lam
+
+
+def _paper_examples():
+    import os
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "slepian_paper_examples.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        L_h, tc, a, lam, pin = line.split()
+        rows.append((int(L_h), float(tc), float(a), float(lam), pin == "yes"))
+    return rows
+
+
+def test_paper_stated_concentration():
+    """The window of the paper's synthetic example and timing experiment (L_h = 18,
+    R_(pi/6, pi/6 + pi/240)) has the concentration the paper states, 90% to the nearest
+    percent (Section V)."""
+    pinned = [r for r in _paper_examples() if r[4]]
+    assert pinned
+    for L_h, tc, a, stated, _ in pinned:
+        _, lam = slepian_window(L_h, tc, a)
+        assert abs(lam - stated) < 0.005, (L_h, lam)
