@@ -352,7 +352,7 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the forward transform shards over l-ranges with no exchange step, but only "
               "the one-GPU kernel is built and measured)", file=sys.stderr)
         sys.exit(2)

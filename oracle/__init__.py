@@ -32,7 +32,7 @@ spherical harmonic transform", IEEE TSP 2013):
                    eqs. Eq:inversion_1, Eq:inversion_2, with the discrete sum
                    of eq. Eq:sig_reconstruction_discrete).
 
-Readings of the paper (band-limits are exclusive here: f_l^m = 0 for l >= L_f,
-h_s^r = 0 for s >= L_h; the beta axis of the SO(3) grid is 2*pi*b/n_phi for
-b = 0..(n_phi-1)/2, as in the definition of E_L) are listed in the design doc.
+Readings of the paper used throughout: band-limits are exclusive (f_l^m = 0 for
+l >= L_f, h_s^r = 0 for s >= L_h), and the beta axis of the SO(3) grid is
+2*pi*b/n_phi for b = 0..(n_phi-1)/2, as in the definition of E_L.
 """
