@@ -176,3 +176,30 @@ def test_matrix_core_phi_stage_sampled(L_h, prec, tol, pair):
     ref = oracle_g_grid(f, h, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, idx)
     errs = per_l_rel_err(gather_rho(g, idx), ref, l_lo, l_hi, axis=1)
     assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("L_h,prec,tol", [(8, "fp64", FP64_TOL), (8, "fp32", FP32_TOL),
+                                          (20, "fp64", FP64_TOL), (20, "fp32", FP32_TOL)])
+def test_largest_phi_grid_sampled(L_h, prec, tol):
+    """n_phi = 2047, the largest supported: 1024 phi slots (several slot chunks per lane in
+    the VALU phi stage, sixteen 64-slot units in the MFMA one), on a ragged 3-row theta
+    slice in the middle of the 1024 theta rows; sampled rotations against the oracle."""
+    announce(f"largest phi grid L_h={L_h} {prec}")
+    rng = np.random.default_rng(18)
+    L_f, l_lo, l_hi, n_phi, n_omega = 7, 5, 9, 2047, 9
+    n_theta, tlo, thi = 1024, 511, 514
+    f = draw_coefficients(rng, L_f)
+    h = draw_window(rng, L_h)
+    plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, precision=prec,
+                                  theta_lo=tlo, theta_hi=thi))
+    g = plan.forward(dev(f), dev(h))
+    idx = np.stack([rng.integers(0, n_phi, 200), rng.integers(0, thi - tlo, 200),
+                    rng.integers(0, n_omega, 200)], 1)
+    idx[0] = (0, 0, 0)
+    idx[1] = (n_phi - 1, thi - tlo - 1, n_omega - 1)
+    idx[2] = (1023, 1, 4)
+    idx[3] = (1024, 2, 8)
+    ref = oracle_g_grid(f, h, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega,
+                        idx + np.array([0, tlo, 0]))
+    errs = per_l_rel_err(gather_rho(g, idx), ref, l_lo, l_hi, axis=1)
+    assert max(errs.values()) <= tol, errs
