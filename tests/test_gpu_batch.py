@@ -57,6 +57,29 @@ def test_batch_uneven_requests_equal_alone():
     _check(cases)
 
 
+def test_batch_theta_slices_and_steerable_windows():
+    """Per-transform arguments that differ only in the theta slice or the steerable limit
+    (all four share the FP64 L_h <= 8 kernel)."""
+    announce("batch theta slices and steerable")
+    rng = np.random.default_rng(75)
+    L_f, L_h = 24, 8
+    n_phi, n_theta, n_omega = grid_dims(L_f, L_h)
+    cases = []
+    for tlo, thi, n_az in ((0, 0, 0), (5, 9, 0), (17, 18, 3), (0, 0, 2)):
+        d = api.make_desc(L_f, L_h, 6, 12, n_phi, n_theta, n_omega, theta_lo=tlo,
+                          theta_hi=thi, n_az=n_az)
+        f = draw_coefficients(rng, L_f, 2.0, True)
+        h = draw_window(rng, L_h)
+        if n_az:
+            for s_ in range(L_h):
+                for r in range(-s_, s_ + 1):
+                    if abs(r) >= n_az:
+                        h[s_ * s_ + s_ + r] = 0
+            h /= np.linalg.norm(h)
+        cases.append((api.Plan(d), dev(f), dev(h)))
+    _check(cases)
+
+
 def test_batch_more_than_one_grid_of_transforms():
     """20 plans sharing one kernel: two grids (16 + 4 transforms)."""
     announce("batch 20 plans")
