@@ -372,10 +372,13 @@ def main():
     results = {}
     outputs = {}
     for prec in ("fp64", "fp32"):
-        plan = api.Plan(api.desc_for(wl, precision=prec), device=0)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        plan = api.Plan(api.desc_for(wl, precision=prec), device=0)   # synchronous
+        plan_ms = (time.perf_counter() - tp) * 1e3
         g_t = plan.empty_output()
         wall, per, cpl = time_forward(plan, f_t, h_t, g_t, args.steps, args.warmup, torch, api)
-        results[prec] = dict(plan=plan, wall=wall, per=per, cpl=cpl,
+        results[prec] = dict(plan=plan, wall=wall, per=per, cpl=cpl, plan_ms=plan_ms,
                              out_bytes=g_t.numel() * g_t.element_size())
         outputs[prec] = g_t
         log(f"{prec}: forward {per.mean():.3f} ms (p50 {np.percentile(per, 50):.3f}, "
@@ -406,6 +409,33 @@ def main():
     log(f"hipMemsetAsync of a buffer the size of the FP64 output: {fill_gbs:.0f} GB/s")
     del g64
     torch.cuda.empty_cache()
+
+    # inverse of the FP64 output (Section III-C): reads all of g once
+    plan64 = results["fp64"]["plan"]
+    f_out = torch.empty(plan64.n_lm, dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+    plan64.inverse(outputs["fp64"], h_t, f_out, stream=stream)
+    torch.cuda.synchronize()
+    iev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(5)]
+    for s_, e_ in iev:
+        s_.record(stream)
+        plan64.inverse(outputs["fp64"], h_t, f_out, stream=stream)
+        e_.record(stream)
+    torch.cuda.synchronize()
+    inv_ms = float(np.mean([s_.elapsed_time(e_) for s_, e_ in iev]))
+    lm0 = wl.l_lo * wl.l_lo
+    f_ref = torch.from_numpy(f[lm0:lm0 + plan64.n_lm]).to(dev)
+    inv_err = float((f_out - f_ref).abs().max() / f_ref.abs().max())
+    inv_bytes = results["fp64"]["out_bytes"]
+    inverse_obj = {"workload": "inverse of the mid FP64 output (11.3 GB read once)",
+                   "ms": inv_ms, "max_rel_err_vs_input": inv_err,
+                   "roofline": {"bound": "hbm", "achieved": inv_bytes / (inv_ms * 1e-3) / 1e9,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": inv_bytes / (inv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    log(f"inverse: {inv_ms:.3f} ms, {inv_bytes / (inv_ms * 1e-3) / 1e9:.0f} GB/s, "
+        f"max rel err vs input {inv_err:.2e}")
+    del f_out
 
     r = results["fp64"]
     ms = float(r["per"].mean())
@@ -445,6 +475,11 @@ def main():
                      "measured_fill_GBps": fill_gbs, "frac_of_measured_fill": achieved / fill_gbs,
                      "kernel_source_sha256_16": digest},
     }
+    line["stages"] = {"plan_ms": r["plan_ms"], "coupling_ms": float(r["cpl"].mean()),
+                      "synthesis_ms": kern_ms,
+                      "note": "plan = Wigner-d table and twiddles (host wall time, once per "
+                              "descriptor); coupling and synthesis per step (HIP events)"}
+    line["inverse_mid"] = inverse_obj
     r32 = results["fp32"]
     ms32 = float(r32["per"].mean())
     k32 = float(r32["per"].mean() - r32["cpl"].mean())
