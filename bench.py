@@ -527,9 +527,16 @@ def main():
             c = torch.as_tensor(idx[:, 2], device=dev)
             got = g[:, c, b, a].transpose(0, 1).cpu().numpy().astype(np.complex128)
             e = rel_err_per_l(got, ref, wl.l_lo, wl.l_hi)
+            per_l = {}
+            for k, l in enumerate(range(wl.l_lo, wl.l_hi)):
+                sl = slice(l * l - wl.l_lo ** 2, (l + 1) ** 2 - wl.l_lo ** 2)
+                per_l[str(l)] = {"rel_frobenius": e[k],
+                                 "max_abs": float(np.abs(got[:, sl] - ref[:, sl]).max())}
             errs[prec] = {"max_rel_frobenius_per_l": max(e),
                           "max_abs": float(np.abs(got - ref).max()),
-                          "max_abs_ref": float(np.abs(ref).max())}
+                          "max_abs_ref": float(np.abs(ref).max()),
+                          "per_l": per_l}
+        errs["rotations"] = int(idx.shape[0])
         line["error_vs_oracle"] = errs
     print(json.dumps(line), flush=True)
 
