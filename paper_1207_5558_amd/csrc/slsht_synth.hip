@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(256) synth_batch_kernel(const SynthBatch b) {
     synth_block<T, LH, NS>(b.r[r], (int)blockIdx.x - b.first[r]);
 }
 
-static int lh_bucket(int L) { return L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : 32)); }
+static int lh_bucket(int L) { return L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 24 ? 24 : 32))); }
 
 static size_t synth_xsize(const DevPlan& P, int tb) {
     const int LH = lh_bucket(P.d.L_h);
@@ -497,6 +497,7 @@ static const void* synth_fn(const DevPlan& P, bool batch = false) {
         case 4: return f64 ? synth_fn_t<double, 4>(ns, batch) : synth_fn_t<float, 4>(ns, batch);
         case 8: return f64 ? synth_fn_t<double, 8>(ns, batch) : synth_fn_t<float, 8>(ns, batch);
         case 16: return f64 ? synth_fn_t<double, 16>(ns, batch) : synth_fn_t<float, 16>(ns, batch);
+        case 24: return f64 ? synth_fn_t<double, 24>(ns, batch) : synth_fn_t<float, 24>(ns, batch);
         default: return f64 ? synth_fn_t<double, 32>(ns, batch) : synth_fn_t<float, 32>(ns, batch);
     }
 }

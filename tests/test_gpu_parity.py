@@ -153,7 +153,7 @@ def test_largest_window_band_limit(prec, tol):
     assert max(errs.values()) <= tol, errs
 
 
-@pytest.mark.parametrize("L_h", [16, 20])
+@pytest.mark.parametrize("L_h", [16, 20, 24])
 @pytest.mark.parametrize("prec,tol,pair", [("fp64", FP64_TOL, False), ("fp64", FP64_TOL, True),
                                            ("fp32", FP32_TOL, True)])
 def test_matrix_core_phi_stage_sampled(L_h, prec, tol, pair):
