@@ -253,11 +253,15 @@ int slsht_slepian_window(int L_h, double theta_c, double a, int device, void* h_
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of forward transforms of uneven size.
  *
- * A server owns one worker thread, device plans cached by descriptor, and an
+ * A server owns one worker thread, device tables cached by descriptor, and an
  * HBM budget for request outputs and inputs.  Requests are admitted in arrival
- * order as budget frees up; every admitted request's kernels are enqueued at
- * once on the server's streams, so transforms of different requests overlap
- * on the device.  Results stay in server-owned device memory until released.
+ * order as budget frees up (a later, smaller request may pass a head that does
+ * not fit yet).  The requests admitted in one scheduling round are launched
+ * together: FULL transforms that share a synthesis kernel run in one grid of up
+ * to 16 transforms (as slsht_forward_batch), each group on the next of the
+ * server's streams, so the work of different requests overlaps on the device.
+ * Results stay in server-owned device memory until released; each equals the
+ * same transform run alone through slsht_forward, bit for bit.
  */
 enum { SLSHT_REQ_QUEUED = 0, SLSHT_REQ_RUNNING = 1, SLSHT_REQ_DONE = 2, SLSHT_REQ_FAILED = 3 };
 
