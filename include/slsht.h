@@ -40,7 +40,10 @@
  *  - Device pointers are HIP device memory owned by the caller; the library
  *    never frees them and keeps no reference after a call returns.  A
  *    `stream` argument is a hipStream_t (NULL = the default stream); work is
- *    enqueued asynchronously on it.
+ *    enqueued asynchronously on it.  slsht_forward, slsht_forward_batch,
+ *    slsht_forward_windows and slsht_coupling enqueue kernels only (no
+ *    allocation, memset or host synchronisation), so they may be captured in
+ *    a HIP graph; slsht_inverse reads h_0^0 on the host and may not.
  *  - Every function returns an slsht_status; nothing throws across the ABI.
  *    Argument checks run on the host before any launch.  The message of the
  *    last failure on the calling thread is available from slsht_last_error().
