@@ -20,20 +20,6 @@ int hip_fail(hipError_t e, const char* what) {
     return slsht::set_error(SLSHT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Saves and restores the caller's current device around a library call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 bool mul_ok(size_t a, size_t b, size_t& r) {
     if (a != 0 && b > std::numeric_limits<size_t>::max() / a) return false;
     r = a * b;
@@ -313,10 +299,7 @@ hipError_t enqueue_forward(const DevPlan& P, const double2* f, const double2* h,
 
 }  // namespace slsht
 
-struct slsht_plan_s {
-    slsht::DevPlan P;
-    int device;
-};
+using slsht::DeviceGuard;
 
 extern "C" {
 

@@ -56,6 +56,22 @@ struct DevPlan {
     size_t lds_bytes = 0;           // dynamic LDS of the synthesis kernel
 };
 
+// Saves and restores the caller's current device around a library call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard&) = delete;
+    DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
+
 // Thread-local error message (slsht_last_error), shared by the host files.
 int set_error(int code, const char* fmt, ...);
 
@@ -115,3 +131,9 @@ constexpr int kEnergyMaxOmega = 64;
 constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 waves, 17 each
 
 }  // namespace slsht
+
+// A public plan: the launch view and its device.
+struct slsht_plan_s {
+    slsht::DevPlan P;
+    int device;
+};

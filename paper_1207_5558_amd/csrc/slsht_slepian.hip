@@ -8,9 +8,9 @@
 // of r.  Its entries
 //   D = c_r c_r' sum_j w_j lam_s^r(theta_j) lam_s'^r'(theta_j) (J_{|r-r'|}(theta_j) +- J_{r+r'}(theta_j)) / 2,
 // with J_k(theta) = int over the region's phi set at theta of cos(k phi), are summed on
-// the GPU in FP64 (one thread per entry); the top eigenvector of each block comes from a
-// Householder reduction to tridiagonal form and implicit QL iterations on the host, and
-// the best of the four is the window.
+// the GPU in FP64 (one thread per entry); the top eigenpair of each block is found on the
+// host (Lanczos with complete reorthogonalisation, Sturm bisection and inverse iteration,
+// eig_top.h), and the best of the four is the window.
 //
 // Quadrature in theta: [0, b] (cos b = cos a / cos theta_c) is the part where the whole
 // circle lies in R, so J_k = 2 pi delta_k0 and the integrand is a polynomial in
@@ -18,6 +18,7 @@
 // exact.  On [b, a] the phi set is |phi| <= phi*, |phi - pi| <= phi*, with phi* ~ the
 // square root of the distance to either end; theta = b + (a - b)(1 - cos(pi t))/2 makes
 // the integrand smooth in t, and Gauss-Legendre in t converges spectrally.
+#include "eig_top.h"
 #include "slsht_device.h"
 
 #include <hip/hip_runtime.h>
@@ -123,118 +124,6 @@ double phi_half_width(double theta, double tc, double a) {
     return 0.5 * (lo + hi);
 }
 
-// Top eigenpair of a real symmetric matrix: Householder reduction to tridiagonal form
-// (accumulating the orthogonal transform), then implicit QL with Wilkinson shifts on
-// the tridiagonal matrix, rotating the accumulated transform.
-double sym_top(std::vector<double>& A, int n, std::vector<double>& vec) {   // A row-major, destroyed
-    // Householder: A = Q T Q^T, T tridiagonal with diagonal d, off-diagonal e
-    std::vector<double> d(n), e(n, 0.0);
-    auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-    for (int i = n - 1; i > 0; --i) {
-        const int l = i - 1;
-        double h = 0.0, scale = 0.0;
-        if (l > 0) {
-            for (int k = 0; k <= l; ++k) scale += std::fabs(a(i, k));
-            if (scale == 0.0) {
-                e[i] = a(i, l);
-            } else {
-                for (int k = 0; k <= l; ++k) {
-                    a(i, k) /= scale;
-                    h += a(i, k) * a(i, k);
-                }
-                double f = a(i, l);
-                double g = f >= 0.0 ? -std::sqrt(h) : std::sqrt(h);
-                e[i] = scale * g;
-                h -= f * g;
-                a(i, l) = f - g;
-                f = 0.0;
-                for (int j = 0; j <= l; ++j) {
-                    a(j, i) = a(i, j) / h;
-                    g = 0.0;
-                    for (int k = 0; k <= j; ++k) g += a(j, k) * a(i, k);
-                    for (int k = j + 1; k <= l; ++k) g += a(k, j) * a(i, k);
-                    e[j] = g / h;
-                    f += e[j] * a(i, j);
-                }
-                const double hh = f / (h + h);
-                for (int j = 0; j <= l; ++j) {
-                    f = a(i, j);
-                    e[j] = g = e[j] - hh * f;
-                    for (int k = 0; k <= j; ++k) a(j, k) -= (f * e[k] + g * a(i, k));
-                }
-            }
-        } else {
-            e[i] = a(i, l);
-        }
-        d[i] = h;
-    }
-    d[0] = 0.0;
-    e[0] = 0.0;
-    for (int i = 0; i < n; ++i) {
-        const int l = i - 1;
-        if (d[i] != 0.0) {
-            for (int j = 0; j <= l; ++j) {
-                double g = 0.0;
-                for (int k = 0; k <= l; ++k) g += a(i, k) * a(k, j);
-                for (int k = 0; k <= l; ++k) a(k, j) -= g * a(k, i);
-            }
-        }
-        d[i] = a(i, i);
-        a(i, i) = 1.0;
-        for (int j = 0; j <= l; ++j) a(j, i) = a(i, j) = 0.0;
-    }
-    // QL with implicit shifts; A now holds Q (columns are the basis)
-    for (int i = 1; i < n; ++i) e[i - 1] = e[i];
-    e[n - 1] = 0.0;
-    for (int l = 0; l < n; ++l) {
-        int iter = 0, m;
-        do {
-            for (m = l; m < n - 1; ++m) {
-                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-16 * dd) break;
-            }
-            if (m != l) {
-                if (++iter > 60) break;
-                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = std::hypot(g, 1.0);
-                g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? std::fabs(r) : -std::fabs(r)));
-                double s = 1.0, c = 1.0, p = 0.0;
-                int i;
-                for (i = m - 1; i >= l; --i) {
-                    double f = s * e[i], b = c * e[i];
-                    e[i + 1] = (r = std::hypot(f, g));
-                    if (r == 0.0) {
-                        d[i + 1] -= p;
-                        e[m] = 0.0;
-                        break;
-                    }
-                    s = f / r;
-                    c = g / r;
-                    g = d[i + 1] - p;
-                    r = (d[i] - g) * s + 2.0 * c * b;
-                    d[i + 1] = g + (p = s * r);
-                    g = c * r - b;
-                    for (int k = 0; k < n; ++k) {
-                        f = a(k, i + 1);
-                        a(k, i + 1) = s * a(k, i) + c * f;
-                        a(k, i) = c * a(k, i) - s * f;
-                    }
-                }
-                if (r == 0.0 && i >= l) continue;
-                d[l] -= p;
-                e[l] = g;
-                e[m] = 0.0;
-            }
-        } while (m != l);
-    }
-    int best = 0;
-    for (int i = 1; i < n; ++i)
-        if (d[i] > d[best]) best = i;
-    vec.resize(n);
-    for (int k = 0; k < n; ++k) vec[k] = a(k, best);
-    return d[best];
-}
-
 }  // namespace
 
 int slepian_window(int L, double tc, double a, double2* h_out, double* conc) {
@@ -302,7 +191,7 @@ int slepian_window(int L, double tc, double a, double2* h_out, double* conc) {
     }
     double best = -1.0;
     std::vector<double> bestvec;
-    int bestb = 0;
+    int bestb = 0, eig_failed = -1;
     for (int bi = 0; bi < 4 && e == hipSuccess; ++bi) {
         Block& B = blocks[bi];
         const int nb = (int)B.s.size();
@@ -318,12 +207,19 @@ int slepian_window(int L, double tc, double a, double2* h_out, double* conc) {
         ok(hipMemcpy(A.data(), dD, A.size() * sizeof(double), hipMemcpyDeviceToHost));
         if (e != hipSuccess) break;
         std::vector<double> v;
-        const double lam = sym_top(A, nb, v);
+        double lam = 0.0;
+        if (sym_top_eigenpair(A, nb, &lam, v) != 0) {
+            eig_failed = bi;
+            break;
+        }
         if (lam > best) { best = lam; bestvec = v; bestb = bi; }
     }
     for (void* p : {(void*)dx, (void*)dw, (void*)dJ, (void*)dlam, (void*)dD, (void*)dbs, (void*)dbr})
         if (p) (void)hipFree(p);
     if (e != hipSuccess) return set_error(SLSHT_EDEVICE, "slepian window: %s", hipGetErrorString(e));
+    if (eig_failed >= 0)
+        return set_error(SLSHT_EDEVICE, "slepian window: the eigenpair of concentration block %d "
+                         "failed its residual check (non-finite or unconverged)", eig_failed);
     // real basis -> complex coefficients; sign: the largest coefficient positive
     const Block& B = blocks[bestb];
     int imax = 0;
