@@ -145,6 +145,21 @@ int slsht_plan_desc(slsht_plan_t plan, slsht_desc* out);
  * symmetry.  Asynchronous on `stream`. */
 int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the transform of
+ * slsht_forward on the same plan, f, h and g, with the coupling scratch taken
+ * from a static device array of SLSHT_NOALLOC_SCRATCH_BYTES per GPU instead of
+ * the plan's own buffer.  The call allocates and frees nothing.  Results equal
+ * slsht_forward's.  The array's device address is resolved once per device, at
+ * the first slsht_plan (or first call) on it.
+ * SLSHT_ETOOBIG if the coupling scratch, (l_hi^2 - l_lo^2) * L_h^2 * 16 bytes,
+ * exceeds SLSHT_NOALLOC_SCRATCH_BYTES.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (on several streams, or from several threads) race; issue them on one
+ * stream.  Asynchronous on `stream`. */
+#define SLSHT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int slsht_forward_noalloc(slsht_plan_t plan, const void* f, const void* h, void* g, void* stream);
+
 /* Coupling stage alone: A[lm][p*p + p + q] = sum_{l'} f_{l'}^{m-q} T(l', m-q; p, q; l, m)
  * = int f Y_p^q conj(Y_l^m) ds, the coefficient that multiplies
  * h_p^{q'} D^p_{q,q'}(rho) in Eq:harmonic_formulation (it equals

@@ -52,6 +52,7 @@ _SIGNATURES = {
     "slsht_plan_destroy": ([_P], ctypes.c_int),
     "slsht_plan_desc": ([_P, ctypes.POINTER(Desc)], ctypes.c_int),
     "slsht_forward": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "slsht_forward_noalloc": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "slsht_forward_windows": ([_P, _P, _P, ctypes.c_int, _P, _P], ctypes.c_int),
     "slsht_factored_workspace": ([ctypes.POINTER(Desc)], ctypes.c_int64),
     "slsht_forward_factored": ([_P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),

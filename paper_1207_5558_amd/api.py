@@ -178,6 +178,20 @@ class Plan:
         L.check(L.lib().slsht_forward(self._h, pf, ph, pg, _stream_handle(stream)))
         return g
 
+    def forward_noalloc(self, f: torch.Tensor, h: torch.Tensor, g: torch.Tensor,
+                        stream=None) -> torch.Tensor:
+        """slsht_forward_noalloc: the same transform with the library's static coupling
+        scratch; g must be given (nothing is allocated)."""
+        d = self.desc
+        n_out = 1
+        for s in self.output_shape:
+            n_out *= s
+        L.check(L.lib().slsht_forward_noalloc(
+            self._h, _dev_ptr(f, torch.complex128, d.L_f * d.L_f, "f"),
+            _dev_ptr(h, torch.complex128, d.L_h * d.L_h, "h"),
+            _dev_ptr(g, self.output_dtype, n_out, "g"), _stream_handle(stream)))
+        return g
+
     def coupling(self, f: torch.Tensor, A: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         d = self.desc
         n = self.n_lm * d.L_h * d.L_h

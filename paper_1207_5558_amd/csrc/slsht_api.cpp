@@ -334,6 +334,9 @@ int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out) {
         return slsht::set_error(SLSHT_EINVAL, "device %d out of range", device);
     DeviceGuard guard(device);
     if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice(%d) failed", device);
+    void* noalloc_ptr = nullptr;      // set-up of slsht_forward_noalloc's scratch address
+    rc = slsht::noalloc_scratch(device, &noalloc_ptr);
+    if (rc) return rc;
 
     std::shared_ptr<slsht::Tables> T;
     rc = slsht::build_tables(*desc, device, T);

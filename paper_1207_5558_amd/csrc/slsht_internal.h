@@ -93,6 +93,9 @@ int make_view(const slsht_desc& d, const std::shared_ptr<Tables>& T, size_t lds_
 hipError_t enqueue_forward(const DevPlan& P, const double2* f, const double2* h, void* g,
                            double2* A, hipStream_t s);
 size_t device_lds_limit(int device);
+// Device address of this GPU's copy of the static scratch array of the allocation-free
+// entry point (slsht_noalloc.hip), resolved once per device with that device current.
+int noalloc_scratch(int device, void** out);
 
 // Launchers; each returns hipSuccess or the launch error.
 hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s);
