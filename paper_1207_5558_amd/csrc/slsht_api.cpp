@@ -2,6 +2,7 @@
 // device tables, plans, and the forward / coupling / inverse entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -70,17 +71,25 @@ struct TableSizes {
     size_t total() const { return dtab + twphi + twom + twfull + qw; }
 };
 
+// ENERGY tiles for table sizes: independent of the LDS split.
+slsht::EnergyGeom energy_tiles(const slsht_desc& d) {
+    slsht::EnergyGeom g{};
+    (void)slsht::energy_geom(d, theta_hi_of(d) - d.theta_lo, (size_t)1 << 30, g);
+    return g;
+}
+
 TableSizes table_sizes(const slsht_desc& d) {
     TableSizes t;
+    const bool energy = d.output_mode == SLSHT_OUT_ENERGY;
     const bool f64 = d.precision == SLSHT_FP64;
-    const size_t rb = f64 ? 8 : 4, vb = f64 ? 16 : 8;
+    const size_t rb = (f64 || energy) ? 8 : 4, vb = f64 ? 16 : 8;
     const int L = d.L_h;
     const size_t nslot = (size_t)(d.n_phi + 1) / 2, ncp = (size_t)d.n_omega / 2 + 1;
     const size_t rows = (size_t)(L > 1 ? L - 1 : 1);
     t.dtab = (size_t)(theta_hi_of(d) - d.theta_lo) * (size_t)slsht::dtab_row_len(L) * rb;
-    t.twphi = rows * nslot * vb;
-    t.twom = rows * ncp * vb;
-    t.twfull = d.output_mode == SLSHT_OUT_ENERGY ? (size_t)d.n_phi * sizeof(float2) : 0;
+    t.twphi = energy ? 0 : rows * nslot * vb;
+    t.twom = energy ? 0 : rows * ncp * vb;
+    t.twfull = energy ? slsht::energy_twiddle_bytes(energy_tiles(d)) : 0;
     t.qw = (size_t)d.n_theta * sizeof(double);
     return t;
 }
@@ -165,6 +174,17 @@ int check_desc(const slsht_desc* d) {
 
 size_t tables_bytes(const slsht_desc& d) { return table_sizes(d).total(); }
 
+size_t energy_workspace_bytes(const slsht_desc& d) {
+    if (d.output_mode != SLSHT_OUT_ENERGY) return 0;
+    // the largest over the LDS sizes a device may report (64 KiB to 160 KiB)
+    size_t best = 0;
+    for (size_t lds : {(size_t)64 << 10, (size_t)160 << 10}) {
+        EnergyGeom g{};
+        if (energy_geom(d, theta_hi_of(d) - d.theta_lo, lds, g)) best = std::max(best, g.total);
+    }
+    return best;
+}
+
 size_t coupling_bytes(const slsht_desc& d) {
     const size_t n_lm = (size_t)d.l_hi * d.l_hi - (size_t)d.l_lo * d.l_lo;
     return n_lm * d.L_h * d.L_h * sizeof(double2);
@@ -212,9 +232,9 @@ int make_view(const slsht_desc& d, const std::shared_ptr<Tables>& T, size_t lds_
     }
     if (P.d.output_mode == SLSHT_OUT_FULL && !choose_synthesis_shape(P, lds_limit))
         return set_error(SLSHT_EINVAL, "no synthesis tiling fits %zu bytes of LDS", lds_limit);
-    if (P.d.output_mode == SLSHT_OUT_ENERGY && energy_lds_for(P) > lds_limit)
-        return set_error(SLSHT_EINVAL, "ENERGY kernel needs %zu bytes of LDS, device allows %zu",
-                         energy_lds_for(P), lds_limit);
+    if (P.d.output_mode == SLSHT_OUT_ENERGY &&
+        (!energy_geom(P.d, P.n_theta_out, lds_limit, P.eg) || energy_lds_for(P) > lds_limit))
+        return set_error(SLSHT_EINVAL, "no ENERGY tiling fits %zu bytes of LDS", lds_limit);
     return SLSHT_OK;
 }
 
@@ -244,7 +264,12 @@ int build_tables(const slsht_desc& d, int device, std::shared_ptr<Tables>& out) 
         return set_error(SLSHT_ENOMEM, "table allocation failed: %s", hipGetErrorString(e));
 
     const int nslot = (d.n_phi + 1) / 2, ncp = d.n_omega / 2 + 1;
-    if (d.precision == SLSHT_FP64) {
+    if (T->energy) {
+        // (cos, sin)(k phi_a) in the fragment order of the ENERGY phi stage
+        std::vector<float> tf;
+        energy_twiddles(energy_tiles(d), tf);
+        e = hipMemcpy(T->tw_full, tf.data(), ts.twfull, hipMemcpyHostToDevice);
+    } else if (d.precision == SLSHT_FP64) {
         std::vector<double> tp, to;
         twiddles(d.L_h, d.n_phi, nslot, tp);
         twiddles(d.L_h, d.n_omega, ncp, to);
@@ -256,16 +281,6 @@ int build_tables(const slsht_desc& d, int device, std::shared_ptr<Tables>& out) 
         twiddles(d.L_h, d.n_omega, ncp, to);
         e = hipMemcpy(T->tw_phi, tp.data(), ts.twphi, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(T->tw_omega, to.data(), ts.twom, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess && ts.twfull) {
-        // cos/sin(2 pi j / n_phi), j < n_phi, for the ENERGY kernel's phi synthesis
-        std::vector<float> tf((size_t)d.n_phi * 2);
-        for (int j = 0; j < d.n_phi; ++j) {
-            const double ang = 2.0 * M_PI * (double)j / (double)d.n_phi;
-            tf[2 * j] = (float)std::cos(ang);
-            tf[2 * j + 1] = (float)std::sin(ang);
-        }
-        e = hipMemcpy(T->tw_full, tf.data(), ts.twfull, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) {
         std::vector<double> qw;
@@ -311,7 +326,9 @@ int slsht_footprint(const slsht_desc* desc, size_t* plan_bytes, size_t* out_byte
                     size_t* scratch_bytes) {
     int rc = slsht::check_desc(desc);
     if (rc) return rc;
-    if (plan_bytes) *plan_bytes = slsht::tables_bytes(*desc) + slsht::coupling_bytes(*desc);
+    if (plan_bytes)
+        *plan_bytes = slsht::tables_bytes(*desc) + slsht::coupling_bytes(*desc) +
+                      slsht::energy_workspace_bytes(*desc);
     if (out_bytes) *out_bytes = slsht::output_bytes(*desc);
     if (scratch_bytes) *scratch_bytes = 0;
     return SLSHT_OK;
@@ -349,9 +366,13 @@ int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out) {
         return rc;
     }
     hipError_t e = hipMalloc((void**)&pl->P.A, slsht::coupling_bytes(*desc));
+    if (e == hipSuccess && desc->output_mode == SLSHT_OUT_ENERGY)
+        e = hipMalloc(&pl->P.ework, pl->P.eg.total);
     if (e != hipSuccess) {
+        if (pl->P.A) (void)hipFree(pl->P.A);
         delete pl;
-        return slsht::set_error(SLSHT_ENOMEM, "coupling scratch: %s", hipGetErrorString(e));
+        return slsht::set_error(SLSHT_ENOMEM, "coupling scratch / workspace: %s",
+                                hipGetErrorString(e));
     }
     *out = pl;
     return SLSHT_OK;
@@ -363,6 +384,7 @@ int slsht_plan_destroy(slsht_plan_t plan) {
         DeviceGuard guard(plan->device);
         (void)hipDeviceSynchronize();
         if (plan->P.A) (void)hipFree(plan->P.A);
+        if (plan->P.ework) (void)hipFree(plan->P.ework);
     }
     delete plan;
     return SLSHT_OK;

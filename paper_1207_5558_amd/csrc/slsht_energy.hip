@@ -1,344 +1,582 @@
-// gfx950 kernel K3e of the directional SLSHT forward path: the ENERGY output
-// E(rho; l) = sum_m |g(rho; l, m)|^2, reduced over the orders m on the fly.
+// gfx950 kernels of the ENERGY output of the directional SLSHT forward path:
+// E(rho; l) = sum_m |g(rho; l, m)|^2, FP32-mixed, reduced over the orders m so that g is
+// never written.
+//
+// The separated form (eq. Eq:alternative_harmonic_formulation_wigner with the separation
+// of variables of Section IV-B) is summed in this order:
+//
+//   W^p_q(theta_b, omega_c) = sum_{|q'| <= p} h_p^{q'} d^p_{q,q'}(theta_b) e^{-i q' omega_c}
+//                                                        (FP64, once per call; no (l, m))
+//   U_q(theta_b, omega_c; l, m) = sum_{p >= |q|} A^p_q(l, m) W^p_q(theta_b, omega_c)
+//                                  (per (theta_b, q) a GEMM over the (l, m) rows, on MFMA)
+//   P_k = U_k + U_{-k},  M_k = -i (U_k - U_{-k})          (k >= 0; P_0 = U_0, M_0 = 0)
+//   g(phi_a) = sum_k cos(k phi_a) P_k + sin(k phi_a) M_k,  g(phi_{n-a}) = same with - sin
+//                           (per (l, theta_b) a GEMM over the phi slots, on MFMA)
+//   E(phi_a) += |g(phi_a)|^2,  E(phi_{n-a}) += |g(phi_{n-a})|^2.
+//
+// The p- and q'-sums are the theta and omega stages of the FULL kernels taken in the other
+// order: the q'-sum no longer depends on (l, m), so it is done once per theta row, and the
+// p-sum becomes a dense contraction shared by all orders.  Kernels per call:
+//   E0 energy_w_kernel      W for every theta row                       -> workspace
+// and per chunk of orders (mc orders of every degree; the P/M slabs of a chunk sit in the
+// workspace, and E is carried across chunks in a partial buffer in register-tile order):
+//   E1 energy_afrag_kernel  A^p_{+-k} of the chunk's (l, m) rows in MFMA fragment order, FP32,
+//                           scaled by sqrt(2) for m > 0 on the real-pair path
+//   E2 energy_u_kernel      U, the fold into P_k, M_k, stored as B fragments of E3
+//   E3 energy_phi_kernel    phi synthesis + |g|^2 accumulation, the bulk of the work
+// MFMA lane layout (v_mfma_f32_16x16x4f32, verified on gfx950): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and receives D rows 4*(l/16)+r, column l%16.
 #include "slsht_device.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace slsht {
 
+namespace {
+
+constexpr int kUWaves = 8;        // E2: one 16-row tile per wave
+constexpr int kPhiWaves = 8;      // E3
+
+// Row offset of W_q (rows p = |q| .. L-1) inside one theta row of W, with q ordered
+// 0, +1, -1, +2, -2, ...; W_{+k} and W_{-k} are adjacent (2 (L-k) rows for k >= 1).
+__host__ __device__ inline int wq_off(int L, int q) {
+    if (q == 0) return 0;
+    const int k = q > 0 ? q : -q;
+    const int base = L + (k - 1) * (2 * L - k);
+    return q > 0 ? base : base + (L - k);
+}
+
+// MFMA k-steps (2 complex degrees each) of the p-sum of U_{+-k}.
+__host__ __device__ inline int u_steps(int L, int k) { return (L - k + 1) / 2; }
+
+__device__ inline int orders_of(const EnergyGeom& g, int l) { return g.real_pair ? l + 1 : 2 * l + 1; }
+
+__device__ inline f4v mfma4(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+}  // namespace
+
+bool energy_geom(const slsht_desc& d, int n_theta_out, size_t lds_limit, EnergyGeom& g) {
+    g = EnergyGeom{};
+    g.L = d.L_h;
+    g.K = 2 * d.L_h - 1;
+    g.KP = (d.L_h + 3) / 4 * 4;
+    g.nkk = g.KP / 4;
+    g.N = n_az_of(d);
+    g.n_phi = d.n_phi;
+    g.n_omega = d.n_omega;
+    const int nct = (d.n_omega + 15) / 16;
+    g.nctp = nct == 3 ? 4 : nct;                       // omega tiles padded to divide 8 waves
+    g.ncw = g.nctp * 16;
+    g.nslot = (d.n_phi + 1) / 2;
+    g.nst = (g.nslot + 15) / 16;
+    g.n_theta_out = n_theta_out;
+    g.theta_lo = d.theta_lo;
+    g.l_lo = d.l_lo;
+    g.n_l = d.l_hi - d.l_lo;
+    g.real_pair = (d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
+    // E3: the block's twiddle fragments live in LDS; split the slot tiles over several
+    // blocks when one (l, theta) row's table does not fit
+    const size_t per_tile = (size_t)g.nkk * 64 * sizeof(float2);
+    const int fit = (int)std::min<size_t>(lds_limit / per_tile, (size_t)g.nst);
+    if (fit < 1) return false;
+    g.nsplit = (g.nst + fit - 1) / fit;
+    g.nstb = (g.nst + g.nsplit - 1) / g.nsplit;
+    g.per = kPhiWaves / g.nctp;
+    const int tpw = (g.nstb + g.per - 1) / g.per;
+    if (tpw > kEnergyMaxTpw) return false;
+    g.tpw = tpw <= 4 ? 4 : (tpw <= 8 ? 8 : (tpw <= 12 ? 12 : kEnergyMaxTpw));   // kernel bucket
+    g.slab = (int64_t)g.nctp * g.nkk * 64 * 4;
+    // orders per chunk: the P/M slabs of one chunk within the workspace budget
+    const int max_orders = g.real_pair ? d.l_hi : 2 * d.l_hi - 1;
+    const size_t per_order = (size_t)g.n_l * n_theta_out * g.slab * sizeof(float);
+    int mc = (int)std::max<size_t>(1, std::min<size_t>(kEnergyChunkBudget / per_order,
+                                                       (size_t)max_orders));
+    g.nchunks = (max_orders + mc - 1) / mc;
+    g.mc = (max_orders + g.nchunks - 1) / g.nchunks;
+    g.rows = g.n_l * g.mc;
+    g.ntiles = (g.rows + 15) / 16;
+    int steps = 0;
+    for (int k = 0; k < g.L; ++k) steps += (k ? 2 : 1) * u_steps(g.L, k);
+    g.afrag_tile = steps * 64;
+    auto al = [](size_t n) { return (n + 255) / 256 * 256; };
+    size_t off = 0;
+    g.off_w = off;
+    off += al((size_t)n_theta_out * g.L * g.L * g.ncw * sizeof(float2));
+    g.off_af = off;
+    off += al((size_t)g.ntiles * g.afrag_tile * sizeof(float));
+    g.off_pm = off;
+    off += al((size_t)g.rows * n_theta_out * g.slab * sizeof(float));
+    g.off_ep = off;
+    if (g.nchunks > 1)
+        off += al((size_t)g.n_l * n_theta_out * g.nsplit * kPhiWaves * g.tpw * 8 * 64 *
+                  sizeof(float));
+    g.total = off;
+    return true;
+}
+
 // ------------------------------------------------------------------------------
-// K3e: energy epilogue, FP32.  One block = one degree l x one theta row; the order m
-// runs inside the block and E(phi_a, theta_b, omega_c; l) = sum_m |g|^2 stays in
-// registers until all orders are done, so g is never written.  The block's canonical
-// Wigner-d row is staged in LDS once.  Per m:
-//   stage 1 (VALU): S_{q,q'}(theta_b) as in K3, d read from LDS          -> LDS
-//   stage 2 (MFMA + VALU): omega synthesis as folded real GEMMs
-//                   X[q][c] = S[q][0] + sum_k (S[q][k] + S[q][-k]) cos(k omega_c),
-//                   Y[q][c] = sum_k (S[q][k] - S[q][-k]) sin(k omega_c), then the fold
-//                   into P_k, M_k, stored k-major with omega contiguous (the B operand
-//                   layout of stage 3)                                        -> LDS
-//   stage 3 (MFMA): the phi synthesis is a real GEMM per part (Re, Im) and per
-//                   cos/sin half:  C[a][c] = sum_k cos(k phi_a) P_k(c),
-//                   S[a][c] = sum_k sin(k phi_a) M_k(c)   (16x16x4 FP32 MFMA),
-//                   then E(a) += |C+S|^2 and E(n-a) += |C-S|^2 elementwise.
-// A fragments (cos/sin(k phi_a)) come from an n_phi-entry cos/sin table in LDS at
-// index k*a mod n_phi, advanced incrementally.  Lane l of a 16x16x4 FP32 MFMA
-// supplies A[l%16][l/16] and B[l/16][l%16] and receives D rows 4*(l/16)+r, column l%16.
+// E0: W^p_q(theta_b, omega_c), one block per (theta row, q).  h_p^{q'} d^p_{q,q'}(theta_b) is
+// staged in LDS (FP64 table entries through the symmetries of Section IV-B); each thread
+// then sums one (p, c) over q' against cos/sin(2 pi j / n_omega) at j = q' c mod n_omega.
+// Columns c >= n_omega (padding of the last omega tile) are written as zeros.
+__global__ void __launch_bounds__(256) energy_w_kernel(const double2* __restrict__ h,
+                                                       const double* __restrict__ dtab,
+                                                       float2* __restrict__ W, const EnergyGeom g) {
+    __shared__ double2 hd[SLSHT_MAX_LH * (2 * SLSHT_MAX_LH - 1)];
+    __shared__ double2 tw[kEnergyMaxOmega];
+    const int L = g.L, K = 2 * L - 1;
+    const int t = blockIdx.x, qi = blockIdx.y;
+    const int k = (qi + 1) / 2;
+    const int q = (qi & 1) ? k : -k;                    // 0, +1, -1, +2, -2, ...
+    const double* drow = dtab + (int64_t)t * dtab_row_len(L);
+    for (int i = threadIdx.x; i < L * K; i += blockDim.x) {
+        const int p = i / K, qp = i - p * K - (L - 1);
+        const int aqp = qp < 0 ? -qp : qp;
+        double2 v = vmk<double2>(0.0, 0.0);
+        if (p >= k && aqp <= p && aqp < g.N) {
+            int Q, Qp;
+            bool neg;
+            d_canonical(q, qp, Q, Qp, neg);
+            const double dv = neg ? -drow[dtab_off(p) + Q * Q + Q + Qp]
+                                  : drow[dtab_off(p) + Q * Q + Q + Qp];
+            const double2 hv = h[p * p + p + qp];
+            v = vmk<double2>(hv.x * dv, hv.y * dv);
+        }
+        hd[i] = v;
+    }
+    for (int j = threadIdx.x; j < g.n_omega; j += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * (double)j / (double)g.n_omega, &s, &c);
+        tw[j] = vmk<double2>(c, s);
+    }
+    __syncthreads();
+    float2* out = W + ((int64_t)t * L * L + wq_off(L, q)) * g.ncw;
+    for (int i = threadIdx.x; i < (L - k) * g.ncw; i += blockDim.x) {
+        const int pr = i / g.ncw, c = i - pr * g.ncw, p = k + pr;
+        double sr = 0.0, si = 0.0;
+        if (c < g.n_omega) {
+            const int P = min(p, g.N - 1);
+            int idx = (int)(((int64_t)(g.n_omega - c) * P) % g.n_omega);     // (-P c) mod n
+            const double2* row = hd + p * K + (L - 1);
+            for (int qp = -P; qp <= P; ++qp) {
+                const double2 hv = row[qp];
+                const double2 e = tw[idx];                                    // e^{-i q' w} = c - i s
+                sr += hv.x * e.x + hv.y * e.y;
+                si += hv.y * e.x - hv.x * e.y;
+                idx += c;
+                if (idx >= g.n_omega) idx -= g.n_omega;
+            }
+        }
+        out[i] = vmk<float2>((float)sr, (float)si);
+    }
+}
 
-struct EnergyArgs {
-    const double2* A;
-    const double2* h;
-    const float* dtab;
-    const float2* twom;
-    const float2* twfull;
-    float* E;
-    int64_t dstride;
-    int L, K, KP, l_lo, n_l, n_phi, n_omega, n_theta_out, nslot, ncp, nst, nct, nctp, cstride;
-    int real_pair, nblk;
-    int N;        // azimuthal band-limit of the window (|q'| < N)
-};
+// ------------------------------------------------------------------------------
+// E1: the chunk's coupling rows in A-fragment order.  Row r of the chunk is degree
+// l_lo + r / mc, order index chunk*mc + r % mc (m = that index - l, or the index itself on the
+// real-pair path); rows past a degree's last order are zero.  Step s of U_{+-k} holds, in lane
+// (i, j4), component (j4 & 1) of A^p_{+-k} with p = k + 2s + (j4 >> 1) for row 16*tile + i.
+__global__ void __launch_bounds__(64) energy_afrag_kernel(const double2* __restrict__ A,
+                                                          float* __restrict__ af,
+                                                          const EnergyGeom g, int chunk) {
+    const int tile = blockIdx.x, lane = threadIdx.x;
+    const int row = tile * 16 + (lane & 15), j4 = lane >> 4;
+    const int L = g.L;
+    const int li = row / g.mc, mj = row - li * g.mc;
+    bool valid = li < g.n_l;
+    int64_t lm = 0;
+    double w = 1.0;
+    if (valid) {
+        const int l = g.l_lo + li;
+        const int mi = chunk * g.mc + mj;
+        valid = mi < orders_of(g, l);
+        const int m = g.real_pair ? mi : mi - l;
+        lm = (int64_t)l * l + l + m - (int64_t)g.l_lo * g.l_lo;
+        // real pair: E = |g_0|^2 + 2 sum_{m>0} |g_m|^2, the weight folded into A
+        if (g.real_pair && m > 0) w = 1.4142135623730951;
+    }
+    float* out = af + (int64_t)tile * g.afrag_tile + lane;
+    int off = 0;
+    for (int k = 0; k < L; ++k) {
+        const int steps = u_steps(L, k);
+        for (int sg = 0; sg < (k ? 2 : 1); ++sg) {
+            const int q = sg ? -k : k;
+            for (int s = 0; s < steps; ++s) {
+                const int p = k + 2 * s + (j4 >> 1);
+                float v = 0.0f;
+                if (valid && p < L) {
+                    const double2 a = A[lm * L * L + p * p + p + q];
+                    v = (float)(w * ((j4 & 1) ? a.y : a.x));
+                }
+                out[(int64_t)(off + s) * 64] = v;
+            }
+            off += steps;
+        }
+    }
+}
 
-constexpr int kEnergyWaves = 8;
-
-// TPW: slot tiles per wave; NKK >= KP/4: k-steps of the MFMA loops, a compile-time bound
-// so that the loops unroll and every A fragment of a tile is loaded before its MFMAs.
-template <int TPW, int NKK>
-__global__ void __launch_bounds__(64 * kEnergyWaves) energy_kernel(const EnergyArgs a) {
+// ------------------------------------------------------------------------------
+// E2: U_{+-k}(theta_b, omega_c) for 16 rows per wave as complex GEMMs on real MFMAs
+// (complex inner index p expanded to (Re, Im), B = [[W_re, W_im], [-W_im, W_re]] row pairs),
+// then P_k, M_k stored as the B fragments of E3: slab (row, theta), entry
+// ((ct * nkk + k / 4) * 64 + (k % 4) * 16 + c % 16) holds float4 (P.re, P.im, M.re, M.im)
+// of omega column c = 16 ct + c % 16.  W_{+-k} of the block's theta row is staged in LDS.
+__global__ void __launch_bounds__(64 * kUWaves) energy_u_kernel(const float2* __restrict__ W,
+                                                                const float* __restrict__ af,
+                                                                float* __restrict__ pm,
+                                                                const EnergyGeom g, int chunk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int L = a.L, K = a.K, KK = K * K, KP = a.KP, cs_ = a.cstride;
-    const int ncw = (a.ncp + 15) / 16 * 16;                      // omega slots, padded
-    const int nqt = (K + 15) / 16;                               // q tiles of the omega GEMM
-    float4* XY = reinterpret_cast<float4*>(smem_raw);            // [nqt*16][ncw] X, Y parts
-    float2* A_s = reinterpret_cast<float2*>(XY + nqt * 16 * ncw);
-    float2* h_s = A_s + L * L;
-    float2* S_s = h_s + L * L;                                   // [K][K], stages 1-2
-    float* PMt = reinterpret_cast<float*>(S_s);                  // [4][KP][cstride], fold and
-                                                                 // stage 3 (S_s is dead by then)
-    float2* tw = S_s + max(KK, 2 * KP * cs_);                    // [n_phi] cos/sin(2 pi j/n_phi)
-    float2* twW = tw + a.n_phi;                                  // [KP][ncw] cos/sin(k omega_cs)
-    float* D_s = reinterpret_cast<float*>(twW + KP * ncw);       // canonical d row of this block
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    float2* Ws = reinterpret_cast<float2*>(smem_raw);   // [<= 2 (L-1) or L rows][ncw]
+    const int L = g.L, ncw = g.ncw;
+    const int t = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.y * kUWaves + wave;
+    const bool active = tile < g.ntiles;
+    const int j4 = lane >> 4, col = lane & 15;
+    const float2* Wt = W + (int64_t)t * L * L * ncw;
+    const float* aft = af + (int64_t)(active ? tile : 0) * g.afrag_tile + lane;
 
-    // XCD-aware order: consecutive logical blocks (same theta row, other degrees) land
-    // on one XCD and share its L2 copy of the Wigner-d row.
-    int bid = blockIdx.x;
-    if ((a.nblk & 7) == 0) bid = (blockIdx.x & 7) * (a.nblk >> 3) + (blockIdx.x >> 3);
-    const int t = bid / a.n_l;
-    const int lidx = bid - t * a.n_l;
-    const int l = a.l_lo + lidx;
-
-    for (int i = tid; i < a.n_phi; i += nth) tw[i] = a.twfull[i];
-    {
-        const float* drow = a.dtab + (int64_t)t * a.dstride;
-        for (int i = tid; i < a.dstride; i += nth) D_s[i] = drow[i];
-    }
-    for (int i = tid; i < KP * ncw; i += nth) {
-        const int k = i / ncw, cs = i - k * ncw;
-        float2 v = vmk<float2>(0.0f, 0.0f);
-        if (cs < a.ncp && k < L) v = k == 0 ? vmk<float2>(1.0f, 0.0f) : a.twom[(k - 1) * a.ncp + cs];
-        twW[i] = v;
-    }
-    for (int i = tid; i < L * L; i += nth) h_s[i] = vcast<float2>(a.h[i]);
-
-    // energy of this wave's tiles (omega tile w % nctp, slot tiles w / nctp + j * 8 / nctp)
-    float Ep[TPW][4], Em[TPW][4];
+    // the four output rows of this lane: 16 * tile + 4 * j4 + r
+    int64_t base[4];
+    bool rv[4];
 #pragma unroll
-    for (int j = 0; j < TPW; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
+    for (int r = 0; r < 4; ++r) {
+        const int row = tile * 16 + 4 * j4 + r;
+        const int li = row / g.mc, mj = row - li * g.mc;
+        rv[r] = active && li < g.n_l && chunk * g.mc + mj < orders_of(g, g.l_lo + li);
+        base[r] = (((int64_t)li * g.n_theta_out + t) * g.mc + mj) * g.slab + (int64_t)col * 4;
+    }
 
-    const int nrep = theta_items(L, a.N);
-    const int nm = a.real_pair ? l + 1 : 2 * l + 1;
-    for (int mi = 0; mi < nm; ++mi) {
-        const int m = a.real_pair ? mi : mi - l;
-        // real pair: E = 2 (|g_0|^2 / 2 + sum_{m>0} |g_m|^2); the m = 0 half-weight is
-        // applied by scaling that order's B fragments by sqrt(1/2), the factor 2 at the store
-        const float bscale = (a.real_pair && m == 0) ? 0.70710678118654752f : 1.0f;
-        const int64_t lm = (int64_t)l * l + l + m - (int64_t)a.l_lo * a.l_lo;
-        for (int i = tid; i < L * L; i += nth) A_s[i] = vcast<float2>(a.A[lm * L * L + i]);
+    // W_{+-k} of the next k is loaded into registers while the MFMAs of this k run
+    // (at most (2L-2) * 64 / 2 float4 over the block's threads: 4 each)
+    constexpr int kWPer = (2 * SLSHT_MAX_LH - 2) * kEnergyMaxOmega / 2 / (64 * kUWaves) + 1;
+    float4 wr[kWPer];
+    auto load_w = [&](int k) {
+        const int n4 = (k ? 2 * (L - k) : L) * ncw / 2;
+        const float4* src = reinterpret_cast<const float4*>(Wt + (int64_t)wq_off(L, k) * ncw);
+#pragma unroll
+        for (int i = 0; i < kWPer; ++i) {
+            const int idx = threadIdx.x + i * 64 * kUWaves;
+            wr[i] = idx < n4 ? src[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    };
+    // the A fragments of the next k likewise (steps <= 16 per sign; L2-resident)
+    float apn[16], amn[16];
+    auto load_a = [&](int k, int off) {
+        const int steps = u_steps(L, k);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            apn[s] = (active && s < steps) ? aft[(int64_t)(off + s) * 64] : 0.0f;
+            amn[s] = (active && k && s < steps) ? aft[(int64_t)(off + steps + s) * 64] : 0.0f;
+        }
+    };
+    load_w(0);
+    load_a(0, 0);
+    int aoff = 0;
+    for (int k = 0; k < L; ++k) {
+        const int steps = u_steps(L, k);
         __syncthreads();
-
-        // stage 1: theta contraction over |q'| < N (see theta_item / theta_pair)
-        for (int j = 0; j * nth < nrep; ++j) {
-            if (tid >= nrep - j * nth) break;
-            int s_, q, qp;
-            theta_item(snake_item(j, tid, nth, nrep), L, a.N, s_, q, qp);
-            float2 v, vm;
-            theta_pair<float, float2, 4>(D_s, A_s, h_s, L, s_, q, qp, v, vm);
-            S_s[(q + L - 1) * K + (qp + L - 1)] = v;
-            if (s_ > 0) S_s[(L - 1 - q) * K + (L - 1 - qp)] = vm;
+        {
+            const int n4 = (k ? 2 * (L - k) : L) * ncw / 2;
+            float4* dst = reinterpret_cast<float4*>(Ws);
+#pragma unroll
+            for (int i = 0; i < kWPer; ++i) {
+                const int idx = threadIdx.x + i * 64 * kUWaves;
+                if (idx < n4) dst[idx] = wr[i];
+            }
         }
         __syncthreads();
-
-        // stage 2: omega synthesis as folded real GEMMs on the MFMA units,
-        //   X[q][c] = S[q][0] + sum_{k>0} (S[q][k] + S[q][-k]) cos(k omega_c)
-        //   Y[q][c] =           sum_{k>0} (S[q][k] - S[q][-k]) sin(k omega_c)
-        // (Re and Im separately), one 16x16 (q, omega-slot) tile per wave and step.
-        for (int it = wave; it < nqt * (ncw / 16); it += kEnergyWaves) {
-            const int qt = it % nqt, ct2 = it / nqt;
-            const int kq2 = lane >> 4, c16 = lane & 15;
-            const int qi = qt * 16 + c16;
-            f4v xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0}, yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+        float ap[16], am[16];
 #pragma unroll
-            for (int kk = 0; kk < NKK; ++kk) {
-                const int k = kk * 4 + kq2;
-                float2 ap = vmk<float2>(0.0f, 0.0f), am = vmk<float2>(0.0f, 0.0f);
-                if (qi < K && k < a.N) {
-                    const float2* row = S_s + qi * K + (L - 1);
-                    if (k == 0) {
-                        ap = row[0];
-                    } else {
-                        const float2 s1 = row[k], s2 = row[-k];
-                        ap = vadd(s1, s2);
-                        am = vsub(s1, s2);
+        for (int s = 0; s < 16; ++s) {
+            ap[s] = apn[s];
+            am[s] = amn[s];
+        }
+        const int aoff_next = aoff + (k ? 2 : 1) * steps;
+        if (k + 1 < L) {
+            load_w(k + 1);
+            load_a(k + 1, aoff_next);
+        }
+        if (active) {
+            const int lastp = L - k - 1;                    // last row of W_{+k}
+            for (int ct = 0; ct < g.nctp; ++ct) {
+                f4v upr = {0, 0, 0, 0}, upi = {0, 0, 0, 0}, umr = {0, 0, 0, 0}, umi = {0, 0, 0, 0};
+                const float2* wcol = Ws + ct * 16 + col;
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    if (s >= steps) break;
+                    // rows past the last degree meet a zero A fragment; clamp them in range
+                    const int rp = min(2 * s + (j4 >> 1), lastp);
+                    const float2 wp = wcol[rp * ncw];
+                    upr = mfma4(ap[s], (j4 & 1) ? -wp.y : wp.x, upr);
+                    upi = mfma4(ap[s], (j4 & 1) ? wp.x : wp.y, upi);
+                    if (k) {
+                        const float2 wm = wcol[(L - k + rp) * ncw];
+                        umr = mfma4(am[s], (j4 & 1) ? -wm.y : wm.x, umr);
+                        umi = mfma4(am[s], (j4 & 1) ? wm.x : wm.y, umi);
                     }
                 }
-                const float2 w = k < KP ? twW[k * ncw + ct2 * 16 + c16] : vmk<float2>(0.0f, 0.0f);
-                xr = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.x, w.x, xr, 0, 0, 0);
-                xi = __builtin_amdgcn_mfma_f32_16x16x4f32(ap.y, w.x, xi, 0, 0, 0);
-                yr = __builtin_amdgcn_mfma_f32_16x16x4f32(am.x, w.y, yr, 0, 0, 0);
-                yi = __builtin_amdgcn_mfma_f32_16x16x4f32(am.y, w.y, yi, 0, 0, 0);
-            }
+                const int64_t e = ((int64_t)(ct * g.nkk + (k >> 2)) * 64 + (k & 3) * 16) * 4;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float4 v;
-                v.x = xr[r]; v.y = xi[r]; v.z = yr[r]; v.w = yi[r];
-                XY[(qt * 16 + 4 * kq2 + r) * ncw + ct2 * 16 + c16] = v;
-            }
-        }
-        __syncthreads();
-
-        // fold q = +-k: U_q(omega_c) = X + Y', U_q(omega_{n-c}) = X - Y' with Y' = -i Y, then
-        // P_k = U_k + U_{-k}, M_k = -i (U_k - U_{-k}); stored k-major, omega contiguous
-        for (int idx = tid; idx < L * a.ncp; idx += nth) {
-            const int qa = idx / a.ncp, cs = idx - qa * a.ncp;
-            const float4 vp = XY[(L - 1 + qa) * ncw + cs];
-            const float4 vm = XY[(L - 1 - qa) * ncw + cs];
-            int c2 = a.n_omega - cs;
-            if (cs == 0 || c2 == cs) c2 = -1;
-            for (int side = 0; side < 2; ++side) {
-                const int c = side == 0 ? cs : c2;
-                if (c < 0) break;
-                const float sg = side == 0 ? 1.0f : -1.0f;
-                const float2 Up = vmk<float2>(vp.x + sg * vp.w, vp.y - sg * vp.z);
-                float2 P, M;
-                if (qa == 0) {
-                    P = Up;
-                    M = vmk<float2>(0, 0);
-                } else {
-                    const float2 Um = vmk<float2>(vm.x + sg * vm.w, vm.y - sg * vm.z);
-                    P = vadd(Up, Um);
-                    M = vmul_mi(vsub(Up, Um));
+                for (int r = 0; r < 4; ++r) {
+                    if (!rv[r]) continue;
+                    float4 v;
+                    v.x = upr[r] + umr[r];
+                    v.y = upi[r] + umi[r];
+                    v.z = upi[r] - umi[r];
+                    v.w = umr[r] - upr[r];
+                    *reinterpret_cast<float4*>(pm + base[r] + e) = v;
                 }
-                PMt[(0 * KP + qa) * cs_ + c] = P.x;
-                PMt[(1 * KP + qa) * cs_ + c] = P.y;
-                PMt[(2 * KP + qa) * cs_ + c] = M.x;
-                PMt[(3 * KP + qa) * cs_ + c] = M.y;
             }
         }
-        // rows L..KP-1 of the B table are read as zeros by stage 3
-        for (int idx = tid; idx < 4 * (KP - L) * cs_; idx += nth) {
-            const int part = idx / ((KP - L) * cs_);
-            const int rem = idx - part * (KP - L) * cs_;
-            PMt[(part * KP + L) * cs_ + rem] = 0.0f;
+        aoff = aoff_next;
+    }
+    // rows k = L .. KP-1 of the last k-step are zero (the phi kernel reads whole steps)
+    for (int k = L; k < g.KP; ++k)
+        for (int ct = 0; ct < g.nctp; ++ct) {
+            const int64_t e = ((int64_t)(ct * g.nkk + (k >> 2)) * 64 + (k & 3) * 16) * 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (rv[r])
+                    *reinterpret_cast<float4*>(pm + base[r] + e) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
-        __syncthreads();
+}
 
-        // stage 3: MFMA phi synthesis and energy accumulation.  Wave w owns omega tile
-        // ct = w % nctp and slot tiles st = w / nctp + j * (waves / nctp), so its B fragments
-        // (P_k, M_k of that omega tile) are loaded once per m and stay in registers across
-        // all its slot tiles.  The lane index is made opaque so that the per-tile index
-        // arithmetic is redone for every m instead of being hoisted out of the m loop.
-        int lane_o = lane;
-        asm volatile("" : "+v"(lane_o));
-        const int kq = lane_o >> 4, col = lane_o & 15;
-        const int nkk = KP / 4;
-        const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
-        float breg[4][NKK];
-        {
-            const int bcol = ct * 16 + col;
+// ------------------------------------------------------------------------------
+// E3: phi synthesis and energy.  One block = one degree l x one theta row x one slot range
+// (all of the row's slots unless the twiddle table must be split), the chunk's orders in a
+// loop.  Wave w owns omega tile ct = w % nctp and slot tiles st = st0 + j * per; per order
+// it loads its B fragments (P_k, M_k of that omega tile, float4 per k-step) from the slab
+// and, per slot tile, runs four real GEMMs [16 slots x k] . [k x 16 omega] with A fragments
+// (cos, sin)(k phi_a) from the LDS table in fragment order (one contiguous 512-B read per
+// k-step), then E(a) += |C + S|^2, E(n - a) += |C - S|^2.  The energies stay in registers
+// over the chunk; between chunks they go to the partial buffer in register order.
+template <int TPW, int NKK>
+__global__ void __launch_bounds__(64 * kPhiWaves) energy_phi_kernel(
+    const float* __restrict__ pm, const float2* __restrict__ twf, float* __restrict__ ep,
+    float* __restrict__ E, const EnergyGeom g, int chunk) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* tws = reinterpret_cast<float2*>(smem_raw);   // [nstb][NKK][64], NKK == g.nkk
+    const int row_blk = blockIdx.x / g.nsplit, sp = blockIdx.x - row_blk * g.nsplit;
+    const int li = row_blk / g.n_theta_out, t = row_blk - li * g.n_theta_out;
+    const int l = g.l_lo + li;
+    const int nm = orders_of(g, l);
+    const int m0 = chunk * g.mc;
+    if (m0 >= nm) return;
+    const int cnt = min(g.mc, nm - m0);
+    const bool first = chunk == 0, last = m0 + cnt >= nm;
+    const int st_lo = sp * g.nstb, st_hi = min(g.nst, st_lo + g.nstb);
+    const int nkk = g.nkk;
+    {
+        const float4* src = reinterpret_cast<const float4*>(twf + (int64_t)st_lo * nkk * 64);
+        float4* dst = reinterpret_cast<float4*>(tws);
+        for (int i = threadIdx.x; i < (st_hi - st_lo) * nkk * 32; i += blockDim.x) dst[i] = src[i];
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = lane >> 4, col = lane & 15;
+    const int ct = wave % g.nctp, st0 = wave / g.nctp, per = g.per;
+
+    float Ep[TPW][4], Em[TPW][4];
+    float4* epb = reinterpret_cast<float4*>(ep) +
+                  ((int64_t)blockIdx.x * kPhiWaves + wave) * TPW * 2 * 64 + lane;
+    if (first) {
 #pragma unroll
-            for (int kk = 0; kk < NKK; ++kk) {
-                const int k = kk * 4 + kq;
+        for (int j = 0; j < TPW; ++j)
 #pragma unroll
-                for (int part = 0; part < 4; ++part)
-                    breg[part][kk] = kk < nkk ? bscale * PMt[(part * KP + k) * cs_ + bcol] : 0.0f;
-            }
-        }
+            for (int r = 0; r < 4; ++r) { Ep[j][r] = 0.0f; Em[j][r] = 0.0f; }
+    } else {
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
-            const int st = st0 + j * sstep;
-            if (st >= a.nst) break;
-            const int as = st * 16 + col;                      // slot of this lane's A rows
-            int step4 = 4 * as;                                // (4 as) mod n_phi, as < n_phi
-            while (step4 >= a.n_phi) step4 -= a.n_phi;
-            int idx = kq * as;                                 // (kq as) mod n_phi, kq < 4
-            while (idx >= a.n_phi) idx -= a.n_phi;
-            // A fragments of all k-steps first (k beyond L meets a zero B row)
-            float2 cz[NKK];
+            const float4 a = epb[(2 * j) * 64], b = epb[(2 * j + 1) * 64];
+            Ep[j][0] = a.x; Ep[j][1] = a.y; Ep[j][2] = a.z; Ep[j][3] = a.w;
+            Em[j][0] = b.x; Em[j][1] = b.y; Em[j][2] = b.z; Em[j][3] = b.w;
+        }
+    }
+    __syncthreads();
+
+    const float4* slab0 = reinterpret_cast<const float4*>(pm + (int64_t)row_blk * g.mc * g.slab) +
+                          (int64_t)ct * nkk * 64 + lane;
+    const int64_t slab4 = g.slab / 4;
+    // B fragments (rows k >= L of a slab hold zeros, so they are used as loaded)
+    float4 b[NKK];
+    auto load_b = [&](int mj) {
+        const float4* sb = slab0 + (int64_t)mj * slab4;
 #pragma unroll
-            for (int kk = 0; kk < NKK; ++kk) {
-                cz[kk] = tw[idx];
-                idx += step4;
-                if (idx >= a.n_phi) idx -= a.n_phi;
-            }
+        for (int kk = 0; kk < NKK; ++kk) b[kk] = sb[kk * 64];
+    };
+    // One float per 128-B line of this wave's part of an order's slab: pulls the order after
+    // next into L2; the value is consumed an order later, so the load never stalls.
+    auto touch_b = [&](int mj) {
+        return reinterpret_cast<const float*>(slab0 - lane + (int64_t)mj * slab4)
+            [(lane % (NKK * 8)) * 32];
+    };
+    // Software pipeline over the tiles of all orders: the MFMAs of tile j are issued first;
+    // then the A fragments of the next tile are loaded and the energy of the previous tile
+    // is updated from its accumulators while tile j's MFMAs occupy the matrix core.  After
+    // the last tile's MFMAs the next order's B fragments are loaded the same way.
+    auto energy_update = [&](int j, const f4v& cre, const f4v& cim, const f4v& sre,
+                             const f4v& sim) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float pr = cre[r] + sre[r], pi = cim[r] + sim[r];
+            const float mr = cre[r] - sre[r], mi = cim[r] - sim[r];
+            Ep[j][r] = fmaf(pi, pi, fmaf(pr, pr, Ep[j][r]));
+            Em[j][r] = fmaf(mi, mi, fmaf(mr, mr, Em[j][r]));
+        }
+        // Materialise this tile's energy here, so that its MFMA accumulators die now
+        // (otherwise the updates sink to the end of the unrolled loop and every tile's
+        // accumulators stay live at once).
+        asm volatile("" : "+v"(Ep[j][0]), "+v"(Ep[j][1]), "+v"(Ep[j][2]), "+v"(Ep[j][3]),
+                     "+v"(Em[j][0]), "+v"(Em[j][1]), "+v"(Em[j][2]), "+v"(Em[j][3]));
+    };
+    load_b(0);
+    float touch = touch_b(min(1, cnt - 1));
+    f4v pcre = {0, 0, 0, 0}, pcim = {0, 0, 0, 0}, psre = {0, 0, 0, 0}, psim = {0, 0, 0, 0};
+    for (int mj = 0; mj < cnt; ++mj) {
+        // The LDS offset is made opaque per order so that the twiddle loads (invariant
+        // over the orders) are not hoisted out of this loop into registers.
+        int tw_lane = lane;
+        asm volatile("" : "+v"(tw_lane));
+        // tiles past the block's range repeat its last tile (never stored)
+        auto tile_tw = [&](int j) {
+            const int st = min(st_lo + st0 + j * per, st_hi - 1);
+            return tws + (st - st_lo) * NKK * 64 + tw_lane;
+        };
+        float2 z[NKK];
+#pragma unroll
+        for (int kk = 0; kk < NKK; ++kk) z[kk] = tile_tw(0)[kk * 64];
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
             f4v cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0}, sre = {0, 0, 0, 0}, sim = {0, 0, 0, 0};
 #pragma unroll
             for (int kk = 0; kk < NKK; ++kk) {
-                cre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].x, breg[0][kk], cre, 0, 0, 0);
-                cim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].x, breg[1][kk], cim, 0, 0, 0);
-                sre = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].y, breg[2][kk], sre, 0, 0, 0);
-                sim = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[kk].y, breg[3][kk], sim, 0, 0, 0);
+                cre = mfma4(z[kk].x, b[kk].x, cre);
+                cim = mfma4(z[kk].x, b[kk].y, cim);
+                sre = mfma4(z[kk].y, b[kk].z, sre);
+                sim = mfma4(z[kk].y, b[kk].w, sim);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            if (j + 1 < TPW) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float pr = cre[r] + sre[r], pi = cim[r] + sim[r];
-                const float mr = cre[r] - sre[r], mi2 = cim[r] - sim[r];
-                Ep[j][r] = fmaf(pi, pi, fmaf(pr, pr, Ep[j][r]));
-                Em[j][r] = fmaf(mi2, mi2, fmaf(mr, mr, Em[j][r]));
+                for (int kk = 0; kk < NKK; ++kk) z[kk] = tile_tw(j + 1)[kk * 64];
+            } else {
+                // next order (the last order reloads itself: clamped, branch-free)
+                asm volatile("" ::"v"(touch));
+                load_b(min(mj + 1, cnt - 1));
+                touch = touch_b(min(mj + 2, cnt - 1));
             }
-            // Materialise this tile's energy here, so that its four MFMA accumulators die
-            // before the next tile starts (otherwise the updates sink to the end of the
-            // unrolled loop and every tile's accumulators stay live at once).
-            asm volatile("" : "+v"(Ep[j][0]), "+v"(Ep[j][1]), "+v"(Ep[j][2]), "+v"(Ep[j][3]),
-                         "+v"(Em[j][0]), "+v"(Em[j][1]), "+v"(Em[j][2]), "+v"(Em[j][3]));
+            // previous tile (at j = 0 the last tile of the previous order; before the first
+            // order its accumulators are zero and add nothing)
+            energy_update(j > 0 ? j - 1 : TPW - 1, pcre, pcim, psre, psim);
+            __builtin_amdgcn_sched_barrier(0);
+            pcre = cre;
+            pcim = cim;
+            psre = sre;
+            psim = sim;
         }
-        __syncthreads();
     }
+    energy_update(TPW - 1, pcre, pcim, psre, psim);
+    asm volatile("" ::"v"(touch));
 
-    // store: lane holds slots st*16 + 4*(lane/16) + r of omega column ct*16 + lane%16
-    const float escale = a.real_pair ? 2.0f : 1.0f;
-    const int kq = lane >> 4, col = lane & 15;
-    const int ct = wave % a.nctp, st0 = wave / a.nctp, sstep = kEnergyWaves / a.nctp;
+    if (!last) {
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            epb[(2 * j) * 64] = make_float4(Ep[j][0], Ep[j][1], Ep[j][2], Ep[j][3]);
+            epb[(2 * j + 1) * 64] = make_float4(Em[j][0], Em[j][1], Em[j][2], Em[j][3]);
+        }
+        return;
+    }
+    // final store: lane holds slots 16 st + 4 kq + r of omega column 16 ct + col
+    const int c = ct * 16 + col;
+    if (c >= g.n_omega) return;
+    float* row = E + (((int64_t)li * g.n_omega + c) * g.n_theta_out + t) * g.n_phi;
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-        const int st = st0 + j * sstep;
-        if (st >= a.nst) break;
-        const int c = ct * 16 + col;
-        if (c >= a.n_omega) continue;
-        float* row = a.E + (((int64_t)lidx * a.n_omega + c) * a.n_theta_out + t) * a.n_phi;
+        const int st = st_lo + st0 + j * per;
+        if (st >= st_hi) break;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int s = st * 16 + 4 * kq + r;
-            if (s >= a.nslot) continue;
-            row[s] = escale * Ep[j][r];
-            if (s > 0) row[a.n_phi - s] = escale * Em[j][r];
+            if (s >= g.nslot) continue;
+            row[s] = Ep[j][r];
+            if (s > 0) row[g.n_phi - s] = Em[j][r];
         }
     }
 }
 
-// Row stride (floats) of the k-major B table: at least nctp*16 columns, and
-// congruent to 16 mod 32 so that the 4 k rows a wave reads land on different banks.
-static int energy_cstride(int nctp) {
-    const int c = nctp * 16;
-    return c % 32 == 0 ? c + 16 : c;
+// Twiddle fragments of E3 (host): entry (st, kk, lane) = (cos, sin)(2 pi (k a mod n_phi) / n_phi),
+// k = 4 kk + lane / 16, a = 16 st + lane % 16; zero for a >= nslot.  Phases reduced in integers.
+void energy_twiddles(const EnergyGeom& g, std::vector<float>& out) {
+    out.assign((size_t)g.nst * g.nkk * 64 * 2, 0.0f);
+    for (int st = 0; st < g.nst; ++st)
+        for (int kk = 0; kk < g.nkk; ++kk)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int k = 4 * kk + lane / 16, a = 16 * st + lane % 16;
+                if (a >= g.nslot) continue;
+                const long long r = ((long long)k * a) % g.n_phi;
+                const double ang = 2.0 * M_PI * (double)r / (double)g.n_phi;
+                const size_t i = (((size_t)st * g.nkk + kk) * 64 + lane) * 2;
+                out[i] = (float)std::cos(ang);
+                out[i + 1] = (float)std::sin(ang);
+            }
 }
 
-static size_t energy_lds_bytes(const DevPlan& P, int KP, int cstride) {
-    const int L = P.d.L_h, K = 2 * L - 1;
-    const int ncw = (P.d.n_omega / 2 + 1 + 15) / 16 * 16, nqt = (K + 15) / 16;
-    const size_t sp = std::max((size_t)K * K, (size_t)2 * KP * cstride);   // S_s | PMt
-    return (size_t)nqt * 16 * ncw * sizeof(float4) + (size_t)2 * L * L * sizeof(float2) +
-           sp * sizeof(float2) + (size_t)P.d.n_phi * sizeof(float2) +
-           (size_t)KP * ncw * sizeof(float2) + (size_t)dtab_row_len(L) * sizeof(float);
+size_t energy_twiddle_bytes(const EnergyGeom& g) { return (size_t)g.nst * g.nkk * 64 * sizeof(float2); }
+
+size_t energy_lds_for(const DevPlan& P) {
+    return (size_t)P.eg.nstb * P.eg.nkk * 64 * sizeof(float2);
 }
 
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
                          hipStream_t s) {
-    EnergyArgs a;
-    a.A = A;
-    a.h = h;
-    a.dtab = reinterpret_cast<const float*>(P.T->dtab);
-    a.twom = reinterpret_cast<const float2*>(P.T->tw_omega);
-    a.twfull = reinterpret_cast<const float2*>(P.T->tw_full);
-    a.E = E;
-    a.dstride = dtab_row_len(P.d.L_h);
-    a.L = P.d.L_h;
-    a.K = 2 * P.d.L_h - 1;
-    a.KP = (P.d.L_h + 3) / 4 * 4;
-    a.l_lo = P.d.l_lo;
-    a.n_l = P.d.l_hi - P.d.l_lo;
-    a.n_phi = P.d.n_phi;
-    a.n_omega = P.d.n_omega;
-    a.n_theta_out = P.n_theta_out;
-    a.nslot = P.nslot_phi;
-    a.ncp = P.ncp_omega;
-    a.nst = (P.nslot_phi + 15) / 16;
-    a.nct = (P.d.n_omega + 15) / 16;
-    a.nctp = a.nct == 3 ? 4 : a.nct;                  // omega tiles padded to divide 8 waves
-    a.cstride = energy_cstride(a.nctp);
-    a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
-    a.nblk = a.n_l * P.n_theta_out;
-    a.N = n_az_of(P.d);
-    const size_t lds = energy_lds_bytes(P, a.KP, a.cstride);
-    const int per = kEnergyWaves / a.nctp;           // waves sharing one omega tile
-    const int tpw = (a.nst + per - 1) / per;
-    const int nkk = a.KP / 4;
-    const int ki = nkk <= 2 ? 0 : (nkk <= 4 ? 1 : 2);
-    const int ti = tpw <= 4 ? 0 : (tpw <= 8 ? 1 : (tpw <= 12 ? 2 : (tpw <= 17 ? 3 : -1)));
-    if (ti < 0) return hipErrorInvalidValue;
-    const void* fns[4][3] = {
-        {(const void*)energy_kernel<4, 2>, (const void*)energy_kernel<4, 4>, (const void*)energy_kernel<4, 8>},
-        {(const void*)energy_kernel<8, 2>, (const void*)energy_kernel<8, 4>, (const void*)energy_kernel<8, 8>},
-        {(const void*)energy_kernel<12, 2>, (const void*)energy_kernel<12, 4>, (const void*)energy_kernel<12, 8>},
-        {(const void*)energy_kernel<17, 2>, (const void*)energy_kernel<17, 4>, (const void*)energy_kernel<17, 8>}};
-    const void* fn = fns[ti][ki];
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    void* args[] = {&a};
-    const hipError_t e = hipLaunchKernel(fn, dim3(a.nblk), dim3(64 * kEnergyWaves), args, lds, s);
+    const EnergyGeom& g = P.eg;
+    char* ws = static_cast<char*>(P.ework);
+    if (!ws) return hipErrorInvalidValue;
+    float2* W = reinterpret_cast<float2*>(ws + g.off_w);
+    float* af = reinterpret_cast<float*>(ws + g.off_af);
+    float* pm = reinterpret_cast<float*>(ws + g.off_pm);
+    float* ep = reinterpret_cast<float*>(ws + g.off_ep);
+    hipLaunchKernelGGL(energy_w_kernel, dim3(g.n_theta_out, 2 * g.L - 1), dim3(256), 0, s, h,
+                       reinterpret_cast<const double*>(P.T->dtab), W, g);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipGetLastError();
-}
 
-size_t energy_lds_for(const DevPlan& P) {
-    const int KP = (P.d.L_h + 3) / 4 * 4;
-    const int nct = (P.d.n_omega + 15) / 16;
-    return energy_lds_bytes(P, KP, energy_cstride(nct == 3 ? 4 : nct));
+    const int ti = g.tpw == 4 ? 0 : (g.tpw == 8 ? 1 : (g.tpw == 12 ? 2 : 3));
+#define SLSHT_PHI_ROW(T)                                                                    \
+    {(const void*)energy_phi_kernel<T, 1>, (const void*)energy_phi_kernel<T, 2>,          \
+     (const void*)energy_phi_kernel<T, 3>, (const void*)energy_phi_kernel<T, 4>,          \
+     (const void*)energy_phi_kernel<T, 5>, (const void*)energy_phi_kernel<T, 6>,          \
+     (const void*)energy_phi_kernel<T, 7>, (const void*)energy_phi_kernel<T, 8>}
+    const void* fns[4][8] = {SLSHT_PHI_ROW(4), SLSHT_PHI_ROW(8), SLSHT_PHI_ROW(12),
+                             SLSHT_PHI_ROW(kEnergyMaxTpw)};
+#undef SLSHT_PHI_ROW
+    const int ki = g.nkk - 1;
+    const void* phi = fns[ti][ki];
+    const size_t lds_phi = energy_lds_for(P);
+    if (lds_phi > 64 * 1024)
+        (void)hipFuncSetAttribute(phi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_phi);
+    const size_t lds_u = (size_t)std::max(g.L, 2 * (g.L - 1)) * g.ncw * sizeof(float2);
+    const float2* twf = reinterpret_cast<const float2*>(P.T->tw_full);
+    const dim3 ugrid(g.n_theta_out, (g.ntiles + kUWaves - 1) / kUWaves);
+    const dim3 pgrid(g.n_l * g.n_theta_out * g.nsplit);
+    for (int c = 0; c < g.nchunks; ++c) {
+        hipLaunchKernelGGL(energy_afrag_kernel, dim3(g.ntiles), dim3(64), 0, s, A, af, g, c);
+        hipLaunchKernelGGL(energy_u_kernel, ugrid, dim3(64 * kUWaves), lds_u, s,
+                           (const float2*)W, (const float*)af, pm, g, c);
+        const float* pmc = pm;
+        void* args[] = {(void*)&pmc, (void*)&twf, (void*)&ep, (void*)&E, (void*)&g, (void*)&c};
+        e = hipLaunchKernel(phi, pgrid, dim3(64 * kPhiWaves), args, lds_phi, s);
+        if (e != hipSuccess) return e;
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace slsht

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <vector>
 
 #include "../../include/slsht.h"
 
@@ -32,13 +33,28 @@ struct Tables {
     int device = 0;
     int L_h = 0, n_phi = 0, n_theta = 0, n_omega = 0, theta_lo = 0, theta_hi = 0, precision = 0;
     bool energy = false;
-    void* dtab = nullptr;       // [n_theta_out][dtab_row_len(L_h)] double or float, canonical
+    void* dtab = nullptr;       // [n_theta_out][dtab_row_len(L_h)] canonical; double for FP64
+                                // and ENERGY plans, float for FP32 FULL plans
     void* tw_phi = nullptr;     // [L_h-1][(n_phi+1)/2] (cos, sin) double2 or float2
     void* tw_omega = nullptr;   // [L_h-1][n_omega/2+1] (cos, sin) double2 or float2
-    void* tw_full = nullptr;    // ENERGY: [n_phi] float2 (cos, sin)(2 pi j / n_phi)
+    void* tw_full = nullptr;    // ENERGY: phi twiddle fragments, float2 [nst][nkk][64]
     double* qw = nullptr;       // [n_theta] beta weights of the inverse
     size_t bytes = 0;
     ~Tables();
+};
+
+// Geometry of the ENERGY path (slsht_energy.hip): MFMA tiles, order chunks and workspace
+// offsets, computed on the host from the descriptor and passed to the kernels by value.
+struct EnergyGeom {
+    int L, K, KP, nkk, N;            // window band-limit, 2L-1, L rounded up to 4, KP/4, n_az
+    int n_phi, n_omega, ncw, nctp;   // grid; omega columns padded to nctp tiles of 16
+    int nslot, nst, nsplit, nstb;    // phi slots, their 16-slot tiles, blocks per row, tiles each
+    int per, tpw;                    // waves per omega tile, slot tiles per wave (kernel bucket)
+    int n_theta_out, theta_lo, l_lo, n_l, real_pair;
+    int mc, nchunks, rows, ntiles;   // orders per chunk, chunks, (l, m) rows and 16-row tiles
+    int afrag_tile;                  // floats of A fragments per 16-row tile
+    int64_t slab;                    // floats of P/M fragments per ((l, m), theta row)
+    size_t off_w, off_af, off_pm, off_ep, total;   // workspace byte offsets and size
 };
 
 // Everything a launch needs for one descriptor.
@@ -54,6 +70,8 @@ struct DevPlan {
     int tb = 1;                     // theta rows per synthesis block
     int block = 256;                // threads per synthesis block
     size_t lds_bytes = 0;           // dynamic LDS of the synthesis kernel
+    EnergyGeom eg{};                // ENERGY plans: tiles, chunks, workspace layout
+    void* ework = nullptr;          // ENERGY plans: workspace of eg.total bytes
 };
 
 // Saves and restores the caller's current device around a library call.
@@ -80,6 +98,8 @@ int check_desc(const slsht_desc* d);
 size_t tables_bytes(const slsht_desc& d);
 size_t coupling_bytes(const slsht_desc& d);
 size_t output_bytes(const slsht_desc& d);
+// Workspace of an ENERGY plan (0 for FULL), the largest over device LDS sizes.
+size_t energy_workspace_bytes(const slsht_desc& d);
 // Tables are keyed by the fields they depend on.
 std::string tables_key(const slsht_desc& d);
 // Builds the device tables for d on `device` (which must be current); synchronises
@@ -121,17 +141,26 @@ constexpr int kSynthBatchMax = 16;
 const void* synthesis_kernel_key(const DevPlan& P);
 hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const* A,
                                   const double2* const* h, void* const* g, int n, hipStream_t s);
+// ENERGY path: W table, A fragments, P/M slabs and partial energies in P.ework.
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
                          hipStream_t s);
+// Host-only: geometry of the ENERGY path for d (false if no tiling fits lds_limit).
+bool energy_geom(const slsht_desc& d, int n_theta_out, size_t lds_limit, EnergyGeom& g);
+// Twiddle fragments (cos, sin)(k phi_a) of the ENERGY phi stage, float pairs.
+void energy_twiddles(const EnergyGeom& g, std::vector<float>& out);
+size_t energy_twiddle_bytes(const EnergyGeom& g);
 hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,
                           hipStream_t s);
 // Chooses tb / block / lds_bytes of the FULL synthesis (host only).
 bool choose_synthesis_shape(DevPlan& P, size_t lds_limit);
 size_t energy_lds_for(const DevPlan& P);
 
-// ENERGY output limits of the MFMA kernel (checked on the host).
+// ENERGY output limits of the MFMA kernels (checked on the host).
 constexpr int kEnergyMaxOmega = 64;
 constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 waves, 17 each
+constexpr int kEnergyMaxTpw = 17;
+// Workspace budget of the P/M slabs of one chunk of orders.
+constexpr size_t kEnergyChunkBudget = (size_t)16 << 30;
 
 }  // namespace slsht
 

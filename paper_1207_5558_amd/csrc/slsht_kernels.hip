@@ -91,7 +91,7 @@ hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s) {
     const int L = P.d.L_h;
     dim3 block(128), grid((L * L + 127) / 128, P.n_theta_out);
     const int64_t rl = dtab_row_len(L);
-    if (P.d.precision == SLSHT_FP64)
+    if (P.d.precision == SLSHT_FP64 || P.d.output_mode == SLSHT_OUT_ENERGY)
         hipLaunchKernelGGL(wigner_table_kernel<double>, grid, block, 0, s, (double*)P.T->dtab, L,
                            P.d.n_phi, P.d.theta_lo, P.n_theta_out, rl);
     else

@@ -127,14 +127,17 @@ struct slsht_server_s {
     struct DevPtrs {
         double2 *f, *h, *A;
         void* g;
+        void* work;
     };
+    // Input block layout: [f][h][A][ENERGY workspace], each 256-B aligned.
     DevPtrs ptrs(Request& r) {
         char* in = base + r.in_off;
         DevPtrs p;
+        const size_t fb = al(r.f.size() * sizeof(double2)), hb = al(r.h.size() * sizeof(double2));
         p.f = reinterpret_cast<double2*>(in);
-        p.h = reinterpret_cast<double2*>(in + al(r.f.size() * sizeof(double2)));
-        p.A = reinterpret_cast<double2*>(in + al(r.f.size() * sizeof(double2)) +
-                                         al(r.h.size() * sizeof(double2)));
+        p.h = reinterpret_cast<double2*>(in + fb);
+        p.A = reinterpret_cast<double2*>(in + fb + hb);
+        p.work = in + fb + hb + al(slsht::coupling_bytes(r.d));
         p.g = base + r.out_off;
         return p;
     }
@@ -157,6 +160,7 @@ struct slsht_server_s {
                 e = hipMemcpyAsync(d.h, r->h.data(), r->h.size() * sizeof(double2),
                                    hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = slsht::launch_coupling(r->P, d.f, d.A, s);
+            r->P.ework = d.work;
             P.push_back(&r->P);
             A.push_back(d.A);
             H.push_back(d.h);
@@ -346,7 +350,7 @@ int slsht_submit(slsht_server_t S, const slsht_desc* desc, const void* f_host, c
     std::memcpy(r->h.data(), h_host, r->h.size() * sizeof(double2));
     r->out_bytes = slsht::output_bytes(*desc);
     r->in_bytes = al(r->f.size() * sizeof(double2)) + al(r->h.size() * sizeof(double2)) +
-                  al(slsht::coupling_bytes(*desc));
+                  al(slsht::coupling_bytes(*desc)) + al(slsht::energy_workspace_bytes(*desc));
     if (al(r->out_bytes) + r->in_bytes > S->budget)
         return slsht::set_error(SLSHT_ETOOBIG, "request needs %zu bytes, budget is %zu",
                                 al(r->out_bytes) + r->in_bytes, S->budget);
