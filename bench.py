@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "g(ρ;ℓ,m) samples/s on 1 MI355X, FP32-mixed vs FP64 at stated error; p99 ms"
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK = 157.3          # TFLOP/s, dense FP32 MFMA (MI355X spec sheet)
 KERNEL = "synth_full_kernel"
 
 
@@ -58,8 +59,9 @@ def committed_traffic(profile_name: str, digest: str):
 
 
 def time_forward(plan, f_t, h_t, g_t, steps, warmup, torch, lib_api):
-    """Average duration (ms) of the forward call and of its coupling stage, from HIP
-    events recorded on the stream the kernels are launched on."""
+    """Durations (ms) of the forward call, of its coupling stage and of the synthesis
+    kernel alone (slsht_synthesize from that coupling), from HIP events recorded on the
+    stream the kernels are launched on."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         plan.forward(f_t, h_t, g_t, stream=stream)
@@ -74,7 +76,7 @@ def time_forward(plan, f_t, h_t, g_t, steps, warmup, torch, lib_api):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per = np.array([s.elapsed_time(e) for s, e in ev])
-    # coupling stage alone, same stream
+    # coupling stage alone, then the synthesis kernel alone from that coupling, same stream
     A = torch.empty((plan.n_lm, plan.desc.L_h ** 2), dtype=torch.complex128, device=g_t.device)
     cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
@@ -84,7 +86,15 @@ def time_forward(plan, f_t, h_t, g_t, steps, warmup, torch, lib_api):
         e.record(stream)
     torch.cuda.synchronize()
     cpl = np.array([s.elapsed_time(e) for s, e in cev])
-    return wall, per, cpl
+    sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for s, e in sev:
+        s.record(stream)
+        plan.synthesize(A, h_t, g_t, stream=stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    syn = np.array([s.elapsed_time(e) for s, e in sev])
+    return wall, per, cpl, syn
 
 
 def cpu_baseline(wl, f, h, budget_s: float):
@@ -107,29 +117,40 @@ def cpu_baseline(wl, f, h, budget_s: float):
     return idx, ref, dt, threads
 
 
-def energy_flops_per_m_theta(wl) -> float:
-    """Algorithmic flops of one (m, theta) pair of the ENERGY kernel: the folded phi
-    GEMMs (cos part K = L_h, sin part K = L_h - 1, real and imaginary parts), the theta
-    contraction over sum_p (2p+1)^2 terms, the folded omega synthesis and |g|^2."""
+def energy_flops_per_m_theta(wl, n_items: int) -> float:
+    """Algorithmic flops per (order, theta row) of the ENERGY path as built: the folded phi
+    GEMMs (cos part K = L_h, sin part K = L_h - 1, real and imaginary parts), the p-sum
+    U_q = sum_p A^p_q W^p_q (sum_q (L_h - |q|) = L_h^2 complex MACs per omega sample), the
+    fold into P_k, M_k, forming g(a), g(n-a) and accumulating |g|^2 (6 per sample), and the
+    W table (sum_p (2p+1)^2 complex MACs per omega sample and theta row) spread over the
+    n_items orders that share it."""
     L, nslot, no = wl.L_h, (wl.n_phi + 1) // 2, wl.n_omega
     phi = 2 * nslot * no * 2 * (L + (L - 1))
-    theta = 10 * L * (4 * L * L - 1) // 3
-    omega = (no // 2 + 1) * L * (L - 1) * 16
-    energy = 4 * no * wl.n_phi
-    return float(phi + theta + omega + energy)
+    u = 8 * L * L * no
+    fold = 4 * (L - 1) * no
+    energy = 6 * wl.n_phi * no
+    w = 8 * no * sum((2 * p + 1) ** 2 for p in range(L)) / n_items
+    return float(phi + u + fold + energy + w)
 
 
-def energy_leg(torch, api, steps):
+def energy_leg(torch, api, steps, n_rot=16):
     """Topography-like workload (L_f=512, L_h=32, l in [100,116), 1087x544x63, FP32-mixed),
-    output reduced to sum_m |g|^2; timed for all orders and for the real-pair path."""
-    from paper_1207_5558_amd.inputs import make_inputs, workload
+    output reduced to sum_m |g|^2; timed for all orders and for the real-pair path, with
+    the error of E against the FP64 oracle on seeded rotations."""
+    from oracle.slsht import oracle_energy, oracle_g_grid
+    from paper_1207_5558_amd.inputs import make_inputs, rho_subset, workload
     wl = workload("large")
     f, h = make_inputs(wl)
     ft, ht = torch.from_numpy(f).to("cuda:0"), torch.from_numpy(h).to("cuda:0")
     out = {"workload": "large: L_f=512, L_h=32, l in [100,116) all m (3456 (l,m)), "
                        "1087 x 544 x 63 grid, FP32-mixed, energy output",
            "samples_per_step": wl.samples}
-    fl = energy_flops_per_m_theta(wl)
+    idx = rho_subset(wl, n_rot, seed=404)
+    t0 = time.perf_counter()
+    E_ref = oracle_energy(oracle_g_grid(f, h, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi,
+                                        wl.n_theta, wl.n_omega, idx), wl.l_lo, wl.l_hi)
+    oracle_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
     for name, pair in (("all_orders", False), ("real_pair", True)):
         plan = api.Plan(api.desc_for(wl, real_pair=pair), device=0)
         E = plan.empty_output()
@@ -137,25 +158,79 @@ def energy_leg(torch, api, steps):
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
-        stream = torch.cuda.current_stream()
         for s_, e_ in ev:
             s_.record(stream)
             plan.forward(ft, ht, E, stream=stream)
             e_.record(stream)
         torch.cuda.synchronize()
         ms = float(np.mean([s_.elapsed_time(e_) for s_, e_ in ev]))
-        n_m_theta = (wl.n_lm if not pair else sum(l + 1 for l in range(wl.l_lo, wl.l_hi))) \
-            * wl.n_theta
+        # energy kernels alone (W table, A fragments, U GEMM, phi + |g|^2) from one coupling
+        A = plan.coupling(ft)
+        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for s_, e_ in sev:
+            s_.record(stream)
+            plan.synthesize(A, ht, E, stream=stream)
+            e_.record(stream)
+        torch.cuda.synchronize()
+        syn_ms = float(np.mean([s_.elapsed_time(e_) for s_, e_ in sev]))
+        n_items = wl.n_lm if not pair else sum(l + 1 for l in range(wl.l_lo, wl.l_hi))
+        fl = energy_flops_per_m_theta(wl, n_items)
+        n_m_theta = n_items * wl.n_theta
         tf = fl * n_m_theta / (ms * 1e-3) / 1e12
+        a = torch.as_tensor(idx[:, 0], device=E.device)
+        b = torch.as_tensor(idx[:, 1], device=E.device)
+        c = torch.as_tensor(idx[:, 2], device=E.device)
+        got = E[:, c, b, a].transpose(0, 1).double().cpu().numpy()       # [rho, l]
+        per_l = {}
+        for k, l in enumerate(range(wl.l_lo, wl.l_hi)):
+            d = got[:, k] - E_ref[:, k]
+            per_l[str(l)] = {"rel_frobenius": float(np.linalg.norm(d) / np.linalg.norm(E_ref[:, k])),
+                             "max_abs": float(np.abs(d).max())}
         out[name] = {"ms_per_step": ms, "value": wl.samples / (ms * 1e-3), "unit": "samples/s",
-                     "roofline": {"bound": "mfma", "achieved": tf, "peak": 157.3,
-                                  "unit": "TFLOP/s", "frac": tf / 157.3,
-                                  "algorithmic_flops_per_launch": fl * n_m_theta}}
-        log(f"energy {name}: {ms:.1f} ms, {wl.samples / (ms * 1e-3):.3e} samples/s, "
-            f"{tf:.1f} TFLOP/s")
-        del E, plan
+                     "energy_kernels_ms": syn_ms,
+                     "roofline": {"bound": "mfma", "achieved": tf, "peak": MFMA_F32_PEAK,
+                                  "unit": "TFLOP/s", "frac": tf / MFMA_F32_PEAK,
+                                  "flops_per_m_theta": fl,
+                                  "algorithmic_flops_per_launch": fl * n_m_theta,
+                                  "note": "whole forward (coupling + energy kernels) per step"},
+                     "error_vs_oracle": {
+                         "max_rel_frobenius_per_l": max(v["rel_frobenius"] for v in per_l.values()),
+                         "max_abs": max(v["max_abs"] for v in per_l.values()),
+                         "max_abs_ref": float(np.abs(E_ref).max()),
+                         "rotations": int(idx.shape[0]), "per_l": per_l}}
+        log(f"energy {name}: {ms:.1f} ms (energy kernels {syn_ms:.1f} ms), "
+            f"{wl.samples / (ms * 1e-3):.3e} samples/s, {tf:.1f} TFLOP/s, max rel err per l "
+            f"{out[name]['error_vs_oracle']['max_rel_frobenius_per_l']:.2e}")
+        del E, plan, A
         torch.cuda.empty_cache()
+    out["oracle_seconds"] = oracle_s
     return out
+
+
+def tiny_leg(torch, api, steps, warmup):
+    """Tiny workload (L_f=8, L_h=3, l < 8, 21 x 11 x 5 grid, FP64): launch-bound, reported
+    for latency only, with its error against the oracle on the whole grid."""
+    from oracle.slsht import oracle_g_full
+    from paper_1207_5558_amd.inputs import make_inputs, workload
+    wl = workload("tiny")
+    f, h = make_inputs(wl)
+    ft, ht = torch.from_numpy(f).to("cuda:0"), torch.from_numpy(h).to("cuda:0")
+    plan = api.Plan(api.desc_for(wl), device=0)
+    g = plan.empty_output()
+    _, per, cpl, syn = time_forward(plan, ft, ht, g, steps, warmup, torch, api)
+    plan.forward(ft, ht, g)
+    torch.cuda.synchronize()
+    ref = oracle_g_full(f, h, wl.L_f, wl.L_h, wl.l_lo, wl.l_hi, wl.n_phi, wl.n_theta, wl.n_omega)
+    got = g.cpu().numpy()
+    return {"workload": "tiny: L_f=8, L_h=3, l in [0,8) all m, 21 x 11 x 5 grid, FP64",
+            "ms_per_step": float(per.mean()), "p50_ms": float(np.percentile(per, 50)),
+            "p99_ms": float(np.percentile(per, 99)), "coupling_ms": float(cpl.mean()),
+            "synthesis_ms": float(syn.mean()), "value": wl.samples / (per.mean() * 1e-3),
+            "unit": "samples/s",
+            "error_vs_oracle": {"max_rel": float(np.abs(got - ref).max() / np.abs(ref).max()),
+                                "max_abs": float(np.abs(got - ref).max()),
+                                "grid": "whole"}}
 
 
 def steerable_leg(torch, api, steps, warmup):
@@ -167,8 +242,8 @@ def steerable_leg(torch, api, steps, warmup):
     ft, ht = torch.from_numpy(f).to("cuda:0"), torch.from_numpy(h).to("cuda:0")
     plan = api.Plan(api.desc_for(wl), device=0)
     g = plan.empty_output()
-    _, per, cpl = time_forward(plan, ft, ht, g, steps, warmup, torch, api)
-    ms, kern = float(per.mean()), float(per.mean() - cpl.mean())
+    _, per, cpl, syn = time_forward(plan, ft, ht, g, steps, warmup, torch, api)
+    ms, kern = float(per.mean()), float(syn.mean())
     L = wl.L_h
     out_b = g.numel() * g.element_size()
     alg = out_b + wl.n_lm * L * L * 16 + L * L * 16 + wl.n_theta * (L * (L + 1) * (2 * L + 1) // 6) * 8
@@ -377,12 +452,14 @@ def main():
         plan = api.Plan(api.desc_for(wl, precision=prec), device=0)   # synchronous
         plan_ms = (time.perf_counter() - tp) * 1e3
         g_t = plan.empty_output()
-        wall, per, cpl = time_forward(plan, f_t, h_t, g_t, args.steps, args.warmup, torch, api)
-        results[prec] = dict(plan=plan, wall=wall, per=per, cpl=cpl, plan_ms=plan_ms,
+        wall, per, cpl, syn = time_forward(plan, f_t, h_t, g_t, args.steps, args.warmup, torch,
+                                           api)
+        results[prec] = dict(plan=plan, wall=wall, per=per, cpl=cpl, syn=syn, plan_ms=plan_ms,
                              out_bytes=g_t.numel() * g_t.element_size())
         outputs[prec] = g_t
         log(f"{prec}: forward {per.mean():.3f} ms (p50 {np.percentile(per, 50):.3f}, "
             f"p99 {np.percentile(per, 99):.3f}), coupling {cpl.mean():.4f} ms, "
+            f"synthesis alone {syn.mean():.3f} ms, "
             f"{samples / (per.mean() * 1e-3):.3e} samples/s")
 
     # the practical write ceiling on this device: hipMemsetAsync of a buffer the size of
@@ -439,7 +516,7 @@ def main():
 
     r = results["fp64"]
     ms = float(r["per"].mean())
-    kern_ms = float(r["per"].mean() - r["cpl"].mean())
+    kern_ms = float(r["syn"].mean())
     # algorithmic bytes of the synthesis kernel per launch: the output written once, plus
     # the Wigner-d table, coupling coefficients, window and twiddles read once
     L = wl.L_h
@@ -478,11 +555,12 @@ def main():
     line["stages"] = {"plan_ms": r["plan_ms"], "coupling_ms": float(r["cpl"].mean()),
                       "synthesis_ms": kern_ms,
                       "note": "plan = Wigner-d table and twiddles (host wall time, once per "
-                              "descriptor); coupling and synthesis per step (HIP events)"}
+                              "descriptor); coupling and synthesis (slsht_synthesize from the "
+                              "coupling) each timed alone with HIP events on the launch stream"}
     line["inverse_mid"] = inverse_obj
     r32 = results["fp32"]
     ms32 = float(r32["per"].mean())
-    k32 = float(r32["per"].mean() - r32["cpl"].mean())
+    k32 = float(r32["syn"].mean())
     table32 = table_bytes // 2
     alg32 = r32["out_bytes"] + wl.n_lm * L * L * 16 + L * L * 16 + table32
     line["fp32_mixed"] = {"value": samples / (ms32 * 1e-3), "ms_per_step": ms32,
@@ -502,6 +580,7 @@ def main():
 
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM
+    line["tiny"] = tiny_leg(torch, api, args.steps, args.warmup)
     if not args.no_energy:
         line["energy_large"] = energy_leg(torch, api, args.steps_energy)
     if not args.no_serve:

@@ -64,6 +64,7 @@ _SIGNATURES = {
     "slsht_slepian_window": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P,
                               ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "slsht_coupling": ([_P, _P, _P, _P], ctypes.c_int),
+    "slsht_synthesize": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "slsht_inverse": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "slsht_server_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)],
                             ctypes.c_int),

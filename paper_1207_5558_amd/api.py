@@ -203,6 +203,21 @@ class Plan:
                                        _stream_handle(stream)))
         return A
 
+    def synthesize(self, A: torch.Tensor, h: torch.Tensor, g: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+        """Synthesis stage alone from a coupling A (slsht_synthesize)."""
+        d = self.desc
+        if g is None:
+            g = self.empty_output()
+        n_out = 1
+        for s in self.output_shape:
+            n_out *= s
+        L.check(L.lib().slsht_synthesize(
+            self._h, _dev_ptr(A, torch.complex128, self.n_lm * d.L_h * d.L_h, "A"),
+            _dev_ptr(h, torch.complex128, d.L_h * d.L_h, "h"),
+            _dev_ptr(g, self.output_dtype, n_out, "g"), _stream_handle(stream)))
+        return g
+
     def coupling_modulated(self, f: torch.Tensor, A: torch.Tensor | None = None,
                            work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """The coupling by the modulated-signal transform (the paper's Appendix A route);

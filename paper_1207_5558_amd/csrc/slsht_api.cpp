@@ -406,6 +406,20 @@ int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream) {
     return SLSHT_OK;
 }
 
+int slsht_synthesize(slsht_plan_t plan, const void* A, const void* h, void* g, void* stream) {
+    if (!plan || !A || !h || !g) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
+    const slsht::DevPlan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    const hipError_t e =
+        P.d.output_mode == SLSHT_OUT_FULL
+            ? slsht::launch_synthesis(P, (const double2*)A, (const double2*)h, g, s)
+            : slsht::launch_energy(P, (const double2*)A, (const double2*)h, (float*)g, s);
+    if (e != hipSuccess) return hip_fail(e, "synthesis launch");
+    return SLSHT_OK;
+}
+
 int slsht_forward(slsht_plan_t plan, const void* f, const void* h, void* g, void* stream) {
     if (!plan || !f || !h || !g) return slsht::set_error(SLSHT_EINVAL, "NULL argument");
     DeviceGuard guard(plan->device);
