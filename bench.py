@@ -348,7 +348,15 @@ def factored_leg(torch, api, L_h=18, L_fs=(18, 34, 66, 130)):
             "tau3_ms": timed(lambda: plan.inverse(g, h, f_out)),
             "coupling_3j_ms": timed(lambda: plan.coupling(f, A3)),
             "separated_ms": timed(lambda: plan.forward(f, h, g)),
+            "separated_synthesis_ms": timed(lambda: plan.synthesize(A3, h, g)),
         }
+        # both syntheses write g once (complex128); the inputs (A, tables) are < 1% of it
+        gb = g.numel() * g.element_size()
+        for key, ms_key in (("roofline_separated_synthesis", "separated_synthesis_ms"),
+                            ("roofline_tau2", "tau2_ms")):
+            ach = gb / (res[ms_key] * 1e-3) / 1e9
+            res[key] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": gb}
         out["points"].append({"L_f": L_f, "n_lm": plan.n_lm, **res})
         log(f"paper route L_f={L_f}: tau1 {res['tau1_ms']:.3f} ms, tau2 {res['tau2_ms']:.3f} ms, "
             f"tau3 {res['tau3_ms']:.3f} ms | 3j coupling {res['coupling_3j_ms']:.3f} ms, "
@@ -360,6 +368,38 @@ def factored_leg(torch, api, L_h=18, L_fs=(18, 34, 66, 130)):
         r = np.log(p1["L_f"] / p0["L_f"])
         for k in ("tau1", "tau2", "tau3"):
             out[f"slope_{k}"] = float(np.log(p1[f"{k}_ms"] / p0[f"{k}_ms"]) / r)
+    return out
+
+
+def full_lh16_leg(torch, api, steps, warmup):
+    """The largest serving shape run alone: L_f=192, L_h=16, l in [184,192) all m (3008
+    (l,m)), 415 x 208 x 31 grid, FULL output in FP64 (128.8 GB) and FP32-mixed (64.4 GB);
+    the synthesis here runs the MFMA phi stage of the band-limit bucket 16."""
+    from paper_1207_5558_amd.inputs import draw_coefficients, draw_window, grid_dims
+    rng = np.random.default_rng(16)
+    L_f, L_h, l_lo, l_hi = 192, 16, 184, 192
+    n_phi, n_theta, n_omega = grid_dims(L_f, L_h)
+    f = torch.from_numpy(draw_coefficients(rng, L_f, 2.0, True)).to("cuda:0")
+    h = torch.from_numpy(draw_window(rng, L_h)).to("cuda:0")
+    out = {"workload": f"L_f={L_f}, L_h={L_h}, l in [{l_lo},{l_hi}) all m, "
+                       f"{n_phi} x {n_theta} x {n_omega} grid, FULL"}
+    for prec in ("fp64", "fp32"):
+        plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega,
+                                      precision=prec), device=0)
+        g = plan.empty_output()
+        _, per, cpl, syn = time_forward(plan, f, h, g, steps, warmup, torch, api)
+        gb = g.numel() * g.element_size()
+        ach = gb / (syn.mean() * 1e-3) / 1e9
+        samples = plan.n_lm * n_phi * n_theta * n_omega
+        out[prec] = {"ms_per_step": float(per.mean()), "synthesis_ms": float(syn.mean()),
+                     "value": samples / (per.mean() * 1e-3), "unit": "samples/s",
+                     "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                  "algorithmic_bytes_per_launch": gb}}
+        log(f"L_h=16 shape {prec}: forward {per.mean():.2f} ms, synthesis {syn.mean():.2f} ms, "
+            f"{ach:.0f} GB/s")
+        del g, plan
+        torch.cuda.empty_cache()
     return out
 
 
@@ -577,6 +617,7 @@ def main():
                                           args.warmup)
         line["slepian_window"] = slepian_leg(api)
         line["factored_route"] = factored_leg(torch, api)
+        line["full_lh16"] = full_lh16_leg(torch, api, 5, 2)
 
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM
