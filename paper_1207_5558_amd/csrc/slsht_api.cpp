@@ -174,15 +174,27 @@ int check_desc(const slsht_desc* d) {
 
 size_t tables_bytes(const slsht_desc& d) { return table_sizes(d).total(); }
 
-size_t energy_workspace_bytes(const slsht_desc& d) {
-    if (d.output_mode != SLSHT_OUT_ENERGY) return 0;
-    // the largest over the LDS sizes a device may report (64 KiB to 160 KiB)
+size_t workspace_bytes(const slsht_desc& d) {
+    const int n_theta_out = theta_hi_of(d) - d.theta_lo;
+    if (d.output_mode == SLSHT_OUT_FULL) {
+        const int64_t n_items = (d.flags & SLSHT_REAL_PAIR)
+                                    ? (int64_t)d.l_hi * (d.l_hi + 1) / 2 - (int64_t)d.l_lo * (d.l_lo + 1) / 2
+                                    : (int64_t)d.l_hi * d.l_hi - (int64_t)d.l_lo * d.l_lo;
+        StagedGeom g{};
+        return staged_geom(d, n_theta_out, (int)n_items, g) ? g.total : 0;
+    }
+    // ENERGY: the largest over the LDS sizes a device may report (64 KiB to 160 KiB)
     size_t best = 0;
     for (size_t lds : {(size_t)64 << 10, (size_t)160 << 10}) {
         EnergyGeom g{};
-        if (energy_geom(d, theta_hi_of(d) - d.theta_lo, lds, g)) best = std::max(best, g.total);
+        if (energy_geom(d, n_theta_out, lds, g)) best = std::max(best, g.total);
     }
     return best;
+}
+
+size_t plan_workspace_bytes(const DevPlan& P) {
+    if (P.d.output_mode == SLSHT_OUT_ENERGY) return P.eg.total;
+    return P.staged ? P.sg.total : 0;
 }
 
 size_t coupling_bytes(const slsht_desc& d) {
@@ -230,6 +242,8 @@ int make_view(const slsht_desc& d, const std::shared_ptr<Tables>& T, size_t lds_
     } else {
         P.n_items = (int)P.n_lm;
     }
+    P.staged = P.d.output_mode == SLSHT_OUT_FULL &&
+               staged_geom(P.d, P.n_theta_out, P.n_items, P.sg);
     if (P.d.output_mode == SLSHT_OUT_FULL && !choose_synthesis_shape(P, lds_limit))
         return set_error(SLSHT_EINVAL, "no synthesis tiling fits %zu bytes of LDS", lds_limit);
     if (P.d.output_mode == SLSHT_OUT_ENERGY &&
@@ -328,7 +342,7 @@ int slsht_footprint(const slsht_desc* desc, size_t* plan_bytes, size_t* out_byte
     if (rc) return rc;
     if (plan_bytes)
         *plan_bytes = slsht::tables_bytes(*desc) + slsht::coupling_bytes(*desc) +
-                      slsht::energy_workspace_bytes(*desc);
+                      slsht::workspace_bytes(*desc);
     if (out_bytes) *out_bytes = slsht::output_bytes(*desc);
     if (scratch_bytes) *scratch_bytes = 0;
     return SLSHT_OK;
@@ -366,8 +380,8 @@ int slsht_plan(const slsht_desc* desc, int device, slsht_plan_t* out) {
         return rc;
     }
     hipError_t e = hipMalloc((void**)&pl->P.A, slsht::coupling_bytes(*desc));
-    if (e == hipSuccess && desc->output_mode == SLSHT_OUT_ENERGY)
-        e = hipMalloc(&pl->P.ework, pl->P.eg.total);
+    const size_t wsb = slsht::plan_workspace_bytes(pl->P);
+    if (e == hipSuccess && wsb) e = hipMalloc(&pl->P.ework, wsb);
     if (e != hipSuccess) {
         if (pl->P.A) (void)hipFree(pl->P.A);
         delete pl;

@@ -38,6 +38,42 @@ __device__ __forceinline__ void lm_of(int lm_abs, int& l, int& m) {
     m = lm_abs - ll * ll - ll;
 }
 
+// Synthesis item -> output slot lm, degree l, order m and the slot of order -m that is
+// filled by conjugate symmetry (-1 if none).  Without REAL_PAIR the items are the lm
+// slots themselves; with it they enumerate (l, m), l_lo <= l, 0 <= m <= l, in order.
+struct Item {
+    int lm, l, m, mirror;
+};
+
+__device__ __forceinline__ Item item_decode(int item, int l_lo, int real_pair) {
+    Item it;
+    if (!real_pair) {
+        lm_of(item + l_lo * l_lo, it.l, it.m);
+        it.lm = item;
+        it.mirror = -1;
+        return it;
+    }
+    const int64_t x = item + (int64_t)l_lo * (l_lo + 1) / 2;   // = l(l+1)/2 + m
+    int l = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(l + 1) * (l + 2) / 2 <= x) ++l;
+    while ((int64_t)l * (l + 1) / 2 > x) --l;
+    it.l = l;
+    it.m = (int)(x - (int64_t)l * (l + 1) / 2);
+    it.lm = l * l + l + it.m - l_lo * l_lo;
+    it.mirror = it.m > 0 ? l * l + l - it.m - l_lo * l_lo : -1;
+    return it;
+}
+
+// Row offset of W_q (rows p = |q| .. L-1) inside one theta row of the W table of the
+// ENERGY and staged FULL paths, with q ordered 0, +1, -1, +2, -2, ...; W_{+k} and W_{-k} are
+// adjacent (2 (L-k) rows for k >= 1), and a theta row holds L^2 rows in all.
+__host__ __device__ inline int wq_off(int L, int q) {
+    if (q == 0) return 0;
+    const int k = q > 0 ? q : -q;
+    const int base = L + (k - 1) * (2 * L - k);
+    return q > 0 ? base : base + (L - k);
+}
+
 // Theta-stage work items.  The K x K entries (q, q') of S are visited ring by ring,
 // s = max(|q|,|q'|) (every entry of ring s sums L - s degrees p, so lanes of a wave share
 // trip counts), and one item covers (q, q') and its mirror (-q, -q'), which reuses the

@@ -17,7 +17,7 @@
 // The p- and q'-sums are the theta and omega stages of the FULL kernels taken in the other
 // order: the q'-sum no longer depends on (l, m), so it is done once per theta row, and the
 // p-sum becomes a dense contraction shared by all orders.  Kernels per call:
-//   E0 energy_w_kernel      W for every theta row                       -> workspace
+//   E0 wtable_kernel        W for every theta row (slsht_staged.hip)    -> workspace
 // and per chunk of orders (mc orders of every degree; the P/M slabs of a chunk sit in the
 // workspace, and E is carried across chunks in a partial buffer in register-tile order):
 //   E1 energy_afrag_kernel  A^p_{+-k} of the chunk's (l, m) rows in MFMA fragment order, FP32,
@@ -40,15 +40,6 @@ namespace {
 
 constexpr int kUWaves = 8;        // E2: one 16-row tile per wave
 constexpr int kPhiWaves = 8;      // E3
-
-// Row offset of W_q (rows p = |q| .. L-1) inside one theta row of W, with q ordered
-// 0, +1, -1, +2, -2, ...; W_{+k} and W_{-k} are adjacent (2 (L-k) rows for k >= 1).
-__host__ __device__ inline int wq_off(int L, int q) {
-    if (q == 0) return 0;
-    const int k = q > 0 ? q : -q;
-    const int base = L + (k - 1) * (2 * L - k);
-    return q > 0 ? base : base + (L - k);
-}
 
 // MFMA k-steps (2 complex degrees each) of the p-sum of U_{+-k}.
 __host__ __device__ inline int u_steps(int L, int k) { return (L - k + 1) / 2; }
@@ -118,63 +109,6 @@ bool energy_geom(const slsht_desc& d, int n_theta_out, size_t lds_limit, EnergyG
                   sizeof(float));
     g.total = off;
     return true;
-}
-
-// ------------------------------------------------------------------------------
-// E0: W^p_q(theta_b, omega_c), one block per (theta row, q).  h_p^{q'} d^p_{q,q'}(theta_b) is
-// staged in LDS (FP64 table entries through the symmetries of Section IV-B); each thread
-// then sums one (p, c) over q' against cos/sin(2 pi j / n_omega) at j = q' c mod n_omega.
-// Columns c >= n_omega (padding of the last omega tile) are written as zeros.
-__global__ void __launch_bounds__(256) energy_w_kernel(const double2* __restrict__ h,
-                                                       const double* __restrict__ dtab,
-                                                       float2* __restrict__ W, const EnergyGeom g) {
-    __shared__ double2 hd[SLSHT_MAX_LH * (2 * SLSHT_MAX_LH - 1)];
-    __shared__ double2 tw[kEnergyMaxOmega];
-    const int L = g.L, K = 2 * L - 1;
-    const int t = blockIdx.x, qi = blockIdx.y;
-    const int k = (qi + 1) / 2;
-    const int q = (qi & 1) ? k : -k;                    // 0, +1, -1, +2, -2, ...
-    const double* drow = dtab + (int64_t)t * dtab_row_len(L);
-    for (int i = threadIdx.x; i < L * K; i += blockDim.x) {
-        const int p = i / K, qp = i - p * K - (L - 1);
-        const int aqp = qp < 0 ? -qp : qp;
-        double2 v = vmk<double2>(0.0, 0.0);
-        if (p >= k && aqp <= p && aqp < g.N) {
-            int Q, Qp;
-            bool neg;
-            d_canonical(q, qp, Q, Qp, neg);
-            const double dv = neg ? -drow[dtab_off(p) + Q * Q + Q + Qp]
-                                  : drow[dtab_off(p) + Q * Q + Q + Qp];
-            const double2 hv = h[p * p + p + qp];
-            v = vmk<double2>(hv.x * dv, hv.y * dv);
-        }
-        hd[i] = v;
-    }
-    for (int j = threadIdx.x; j < g.n_omega; j += blockDim.x) {
-        double s, c;
-        sincospi(2.0 * (double)j / (double)g.n_omega, &s, &c);
-        tw[j] = vmk<double2>(c, s);
-    }
-    __syncthreads();
-    float2* out = W + ((int64_t)t * L * L + wq_off(L, q)) * g.ncw;
-    for (int i = threadIdx.x; i < (L - k) * g.ncw; i += blockDim.x) {
-        const int pr = i / g.ncw, c = i - pr * g.ncw, p = k + pr;
-        double sr = 0.0, si = 0.0;
-        if (c < g.n_omega) {
-            const int P = min(p, g.N - 1);
-            int idx = (int)(((int64_t)(g.n_omega - c) * P) % g.n_omega);     // (-P c) mod n
-            const double2* row = hd + p * K + (L - 1);
-            for (int qp = -P; qp <= P; ++qp) {
-                const double2 hv = row[qp];
-                const double2 e = tw[idx];                                    // e^{-i q' w} = c - i s
-                sr += hv.x * e.x + hv.y * e.y;
-                si += hv.y * e.x - hv.x * e.y;
-                idx += c;
-                if (idx >= g.n_omega) idx -= g.n_omega;
-            }
-        }
-        out[i] = vmk<float2>((float)sr, (float)si);
-    }
 }
 
 // ------------------------------------------------------------------------------
@@ -329,8 +263,8 @@ __global__ void __launch_bounds__(64 * kUWaves) energy_u_kernel(const float2* __
                     float4 v;
                     v.x = upr[r] + umr[r];
                     v.y = upi[r] + umi[r];
-                    v.z = upi[r] - umi[r];
-                    v.w = umr[r] - upr[r];
+                    v.z = k ? upi[r] - umi[r] : 0.0f;                // M_0 = 0
+                    v.w = k ? umr[r] - upr[r] : 0.0f;
                     *reinterpret_cast<float4*>(pm + base[r] + e) = v;
                 }
             }
@@ -542,9 +476,8 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
     float* af = reinterpret_cast<float*>(ws + g.off_af);
     float* pm = reinterpret_cast<float*>(ws + g.off_pm);
     float* ep = reinterpret_cast<float*>(ws + g.off_ep);
-    hipLaunchKernelGGL(energy_w_kernel, dim3(g.n_theta_out, 2 * g.L - 1), dim3(256), 0, s, h,
-                       reinterpret_cast<const double*>(P.T->dtab), W, g);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_wtable(P.T->dtab, true, h, W, false, g.L, g.N, g.n_omega, g.ncw,
+                                 g.n_theta_out, s);
     if (e != hipSuccess) return e;
 
     const int ti = g.tpw == 4 ? 0 : (g.tpw == 8 ? 1 : (g.tpw == 12 ? 2 : 3));

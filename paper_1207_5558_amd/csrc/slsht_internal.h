@@ -57,6 +57,17 @@ struct EnergyGeom {
     size_t off_w, off_af, off_pm, off_ep, total;   // workspace byte offsets and size
 };
 
+// Geometry of the staged FULL synthesis (slsht_staged.hip; window band-limits above 16,
+// n_omega <= 64): U GEMM over chunks of items, then the phi stage from the P/M rows.
+struct StagedGeom {
+    int L, N, PW, n_omega, ncw;      // band-limit, n_az, L rounded up to 4, omega (padded)
+    int n_theta_out, l_lo, real_pair, f64;
+    int n_items, ichunk, nchunks, ntiles;   // items, items per chunk (16s), chunks, tiles
+    int afrag_tile;                  // elements of A fragments per 16-item tile
+    int64_t pm_item;                 // complex elements of P/M rows per item
+    size_t off_w, off_af, off_pm, total;   // workspace byte offsets and size
+};
+
 // Everything a launch needs for one descriptor.
 struct DevPlan {
     slsht_desc d{};                 // theta_hi resolved
@@ -71,7 +82,10 @@ struct DevPlan {
     int block = 256;                // threads per synthesis block
     size_t lds_bytes = 0;           // dynamic LDS of the synthesis kernel
     EnergyGeom eg{};                // ENERGY plans: tiles, chunks, workspace layout
-    void* ework = nullptr;          // ENERGY plans: workspace of eg.total bytes
+    bool staged = false;            // FULL plans synthesised by the staged path
+    StagedGeom sg{};                // staged FULL plans: chunks, workspace layout
+    void* ework = nullptr;          // ENERGY / staged plans: workspace of
+                                    // workspace_bytes(*this) bytes
 };
 
 // Saves and restores the caller's current device around a library call.
@@ -98,8 +112,9 @@ int check_desc(const slsht_desc* d);
 size_t tables_bytes(const slsht_desc& d);
 size_t coupling_bytes(const slsht_desc& d);
 size_t output_bytes(const slsht_desc& d);
-// Workspace of an ENERGY plan (0 for FULL), the largest over device LDS sizes.
-size_t energy_workspace_bytes(const slsht_desc& d);
+// Workspace of an ENERGY plan (the largest over device LDS sizes) or of a staged FULL
+// plan; 0 for other FULL plans.
+size_t workspace_bytes(const slsht_desc& d);
 // Tables are keyed by the fields they depend on.
 std::string tables_key(const slsht_desc& d);
 // Builds the device tables for d on `device` (which must be current); synchronises
@@ -144,6 +159,20 @@ hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const*
 // ENERGY path: W table, A fragments, P/M slabs and partial energies in P.ework.
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
                          hipStream_t s);
+// W^p_q(theta_b, omega_c) = sum_{q'} h_p^{q'} d^p_{q,q'}(theta_b) e^{-i q' omega_c} for every
+// theta row of the table (slsht_staged.hip): d in FP64 (d64) or FP32, W stored complex128
+// (w64) or complex64 as [theta][wq_off(q) + p - |q|][ncw].
+hipError_t launch_wtable(const void* dtab, bool d64, const double2* h, void* W, bool w64, int L,
+                         int N, int n_omega, int ncw, int n_theta_out, hipStream_t s);
+// Staged FULL synthesis: geometry (false if the plan does not qualify) and launch.
+bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& g);
+hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const double2* h, void* g,
+                                   hipStream_t s);
+// Phi stage + store of the FULL kernel from P/M rows of items [item0, item0 + n).
+hipError_t launch_synthesis_pm(const DevPlan& P, const void* pm, int item0, int n, void* g,
+                               hipStream_t s);
+// Workspace bytes of a plan view (ENERGY or staged FULL; 0 otherwise).
+size_t plan_workspace_bytes(const DevPlan& P);
 // Host-only: geometry of the ENERGY path for d (false if no tiling fits lds_limit).
 bool energy_geom(const slsht_desc& d, int n_theta_out, size_t lds_limit, EnergyGeom& g);
 // Twiddle fragments (cos, sin)(k phi_a) of the ENERGY phi stage, float pairs.
@@ -161,6 +190,8 @@ constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 wave
 constexpr int kEnergyMaxTpw = 17;
 // Workspace budget of the P/M slabs of one chunk of orders.
 constexpr size_t kEnergyChunkBudget = (size_t)16 << 30;
+// Workspace budget of the P/M rows of one chunk of items (staged FULL path).
+constexpr size_t kStagedChunkBudget = (size_t)4 << 30;
 
 }  // namespace slsht
 

@@ -129,7 +129,7 @@ struct slsht_server_s {
         void* g;
         void* work;
     };
-    // Input block layout: [f][h][A][ENERGY workspace], each 256-B aligned.
+    // Input block layout: [f][h][A][ENERGY or staged-synthesis workspace], each 256-B aligned.
     DevPtrs ptrs(Request& r) {
         char* in = base + r.in_off;
         DevPtrs p;
@@ -350,7 +350,7 @@ int slsht_submit(slsht_server_t S, const slsht_desc* desc, const void* f_host, c
     std::memcpy(r->h.data(), h_host, r->h.size() * sizeof(double2));
     r->out_bytes = slsht::output_bytes(*desc);
     r->in_bytes = al(r->f.size() * sizeof(double2)) + al(r->h.size() * sizeof(double2)) +
-                  al(slsht::coupling_bytes(*desc)) + al(slsht::energy_workspace_bytes(*desc));
+                  al(slsht::coupling_bytes(*desc)) + al(slsht::workspace_bytes(*desc));
     if (al(r->out_bytes) + r->in_bytes > S->budget)
         return slsht::set_error(SLSHT_ETOOBIG, "request needs %zu bytes, budget is %zu",
                                 al(r->out_bytes) + r->in_bytes, S->budget);

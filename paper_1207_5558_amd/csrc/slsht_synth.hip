@@ -42,6 +42,9 @@ struct SynthArgs {
     int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp, l_lo, real_pair;
     int N;        // azimuthal band-limit of the window (|q'| < N)
     int xsize;    // elements of the A/h | P/M union region in LDS
+    int item0;    // first item of this launch (chunks of the staged path)
+    const void* pm;     // staged path: P/M rows [item - item0][theta][2 PW][pm_ncw]
+    int pm_ncw;
 };
 
 struct SynthBatch {
@@ -49,32 +52,6 @@ struct SynthBatch {
     int first[kSynthBatchMax + 1];
     int n;
 };
-
-// Synthesis item -> output slot lm, degree l, order m and the slot of order -m that is
-// filled by conjugate symmetry (-1 if none).  Without REAL_PAIR the items are the lm
-// slots themselves; with it they enumerate (l, m), l_lo <= l, 0 <= m <= l, in order.
-struct Item {
-    int lm, l, m, mirror;
-};
-
-__device__ __forceinline__ Item item_decode(int item, int l_lo, int real_pair) {
-    Item it;
-    if (!real_pair) {
-        lm_of(item + l_lo * l_lo, it.l, it.m);
-        it.lm = item;
-        it.mirror = -1;
-        return it;
-    }
-    const int64_t x = item + (int64_t)l_lo * (l_lo + 1) / 2;   // = l(l+1)/2 + m
-    int l = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-    while ((int64_t)(l + 1) * (l + 2) / 2 <= x) ++l;
-    while ((int64_t)l * (l + 1) / 2 > x) --l;
-    it.l = l;
-    it.m = (int)(x - (int64_t)l * (l + 1) / 2);
-    it.lm = l * l + l + it.m - l_lo * l_lo;
-    it.mirror = it.m > 0 ? l * l + l - it.m - l_lo * l_lo : -1;
-    return it;
-}
 
 template <typename T> struct MfmaOf;
 template <> struct MfmaOf<float> {
@@ -163,7 +140,8 @@ __device__ __forceinline__ void load_phi_b(const typename VecOf<T>::type* __rest
 }
 
 // One block of one transform: block `bid` of the grid that a.n_items x a.n_tiles blocks form.
-template <typename T, int LH, int NS>
+// PMIN: the P/M rows come from the staged path's U GEMM (a.pm) instead of stages 1-2.
+template <typename T, int LH, int NS, bool PMIN = false>
 __device__ __forceinline__ void synth_block(const SynthArgs& a, const int bid) {
     using V = typename VecOf<T>::type;
     using MF = MfmaOf<T>;
@@ -176,88 +154,101 @@ __device__ __forceinline__ void synth_block(const SynthArgs& a, const int bid) {
     // stage the k-steps that cover L
     const int PW = LH <= 8 ? LH : (L + 3) / 4 * 4;
     const int PMS = 2 * PW + 1;                  // complex stride of one P|M row
-    V* X_s = S_s + a.tb * K * K;
+    V* X_s = PMIN ? S_s : S_s + a.tb * K * K;
     V* A_s = X_s;
     V* h_s = X_s + L * L;
     V* PM_s = X_s;                               // [c*tb + t][P_0..P_{PW-1} M_0..M_{PW-1}]
     V* TW_s = X_s + a.xsize;                     // [L-1][ncp] omega twiddles
 
-    const int item = bid / a.n_tiles;
-    const int tile = bid - item * a.n_tiles;
-    const Item it = item_decode(item, a.l_lo, a.real_pair);
+    const int item_rel = bid / a.n_tiles;
+    const int tile = bid - item_rel * a.n_tiles;
+    const Item it = item_decode(a.item0 + item_rel, a.l_lo, a.real_pair);
     const int t0 = tile * a.tb;
     const int tb = min(a.tb, a.n_theta_out - t0);
     const int tid = threadIdx.x, nth = blockDim.x;
 
-    const V* twg = reinterpret_cast<const V*>(a.twom);
-    for (int i = tid; i < L * L; i += nth) {
-        A_s[i] = vcast<V>(a.A[(int64_t)it.lm * L * L + i]);
-        h_s[i] = vcast<V>(a.h[i]);
-    }
-    for (int i = tid; i < (L - 1) * a.ncp; i += nth) TW_s[i] = twg[i];
-    __syncthreads();
-
-    // stage 1: theta contraction over |q'| < N (see theta_item / theta_pair)
-    const T* dt = reinterpret_cast<const T*>(a.dtab);
-    const int KK = K * K;
-    const int nrep = theta_items(L, a.N);
-    for (int j = 0; j * nth < tb * nrep; ++j) {
-        if (tid >= tb * nrep - j * nth) break;
-        const int idx = snake_item(j, tid, nth, tb * nrep);
-        const int t = idx / nrep;
-        int s_, q, qp;
-        theta_item(idx - t * nrep, L, a.N, s_, q, qp);
-        V v, vm;
-        theta_pair<T, V, (sizeof(T) == 8 ? 4 : 8)>(dt + (int64_t)(t0 + t) * a.dstride, A_s, h_s, L, s_, q, qp, v, vm);
-        S_s[t * KK + (q + L - 1) * K + (qp + L - 1)] = v;
-        if (s_ > 0) S_s[t * KK + (L - 1 - q) * K + (L - 1 - qp)] = vm;
-    }
-    __syncthreads();
-
-    // stage 2: omega synthesis, folded into P/M
-    const V* twom = TW_s;
-    const int per_t = a.ncp * L;
-    for (int idx = tid; idx < tb * per_t; idx += nth) {
-        const int t = idx / per_t;
-        const int r = idx - t * per_t;
-        const int cs = r / L;
-        const int qa = r - cs * L;
-        const V* Sp = S_s + t * KK + (qa + L - 1) * K;
-        const V* Sm = S_s + t * KK + (L - 1 - qa) * K;
-        V Xp = Sp[L - 1], Xm = Sm[L - 1];
-        V Yp = vmk<V>(0, 0), Ym = vmk<V>(0, 0);
-        for (int k = 1; k < a.N; ++k) {
-            const V tw = twom[(k - 1) * a.ncp + cs];
-            const V a1 = Sp[L - 1 + k], a2 = Sp[L - 1 - k];
-            const V b1 = Sm[L - 1 + k], b2 = Sm[L - 1 - k];
-            Xp.x += (a1.x + a2.x) * tw.x; Xp.y += (a1.y + a2.y) * tw.x;
-            Yp.x += (a1.x - a2.x) * tw.y; Yp.y += (a1.y - a2.y) * tw.y;
-            Xm.x += (b1.x + b2.x) * tw.x; Xm.y += (b1.y + b2.y) * tw.x;
-            Ym.x += (b1.x - b2.x) * tw.y; Ym.y += (b1.y - b2.y) * tw.y;
+    if constexpr (PMIN) {
+        // P/M rows of the tile's theta rows: global [theta][kslot][c] -> LDS [(c, theta)][kslot]
+        const V* src = reinterpret_cast<const V*>(a.pm) +
+                       ((int64_t)item_rel * a.n_theta_out + t0) * 2 * PW * a.pm_ncw;
+        const int per_t = 2 * PW * a.n_omega;
+        for (int i = tid; i < tb * per_t; i += nth) {
+            const int t = i / per_t, r = i - t * per_t;
+            const int ks = r / a.n_omega, c = r - ks * a.n_omega;
+            PM_s[(c * tb + t) * PMS + ks] = src[((int64_t)t * 2 * PW + ks) * a.pm_ncw + c];
         }
-        Yp = vmul_mi(Yp);
-        Ym = vmul_mi(Ym);
-        const int c1 = cs;
-        int c2 = a.n_omega - cs;
-        if (cs == 0 || c2 == cs) c2 = -1;
-        for (int side = 0; side < 2; ++side) {
-            const int c = side == 0 ? c1 : c2;
-            if (c < 0) break;
-            const V Up = side == 0 ? vadd(Xp, Yp) : vsub(Xp, Yp);
-            V* P = PM_s + (c * tb + t) * PMS;
-            V* M = P + PW;
-            if (qa == 0) {
-                P[0] = Up;
-                M[0] = vmk<V>(0, 0);
-                for (int k = L; k < PW; ++k) { P[k] = vmk<V>(0, 0); M[k] = vmk<V>(0, 0); }
-            } else {
-                const V Um = side == 0 ? vadd(Xm, Ym) : vsub(Xm, Ym);
-                P[qa] = vadd(Up, Um);
-                M[qa] = vmul_mi(vsub(Up, Um));
+        __syncthreads();
+    } else {
+        const V* twg = reinterpret_cast<const V*>(a.twom);
+        for (int i = tid; i < L * L; i += nth) {
+            A_s[i] = vcast<V>(a.A[(int64_t)it.lm * L * L + i]);
+            h_s[i] = vcast<V>(a.h[i]);
+        }
+        for (int i = tid; i < (L - 1) * a.ncp; i += nth) TW_s[i] = twg[i];
+        __syncthreads();
+
+        // stage 1: theta contraction over |q'| < N (see theta_item / theta_pair)
+        const T* dt = reinterpret_cast<const T*>(a.dtab);
+        const int KK = K * K;
+        const int nrep = theta_items(L, a.N);
+        for (int j = 0; j * nth < tb * nrep; ++j) {
+            if (tid >= tb * nrep - j * nth) break;
+            const int idx = snake_item(j, tid, nth, tb * nrep);
+            const int t = idx / nrep;
+            int s_, q, qp;
+            theta_item(idx - t * nrep, L, a.N, s_, q, qp);
+            V v, vm;
+            theta_pair<T, V, (sizeof(T) == 8 ? 4 : 8)>(dt + (int64_t)(t0 + t) * a.dstride, A_s, h_s, L, s_, q, qp, v, vm);
+            S_s[t * KK + (q + L - 1) * K + (qp + L - 1)] = v;
+            if (s_ > 0) S_s[t * KK + (L - 1 - q) * K + (L - 1 - qp)] = vm;
+        }
+        __syncthreads();
+
+        // stage 2: omega synthesis, folded into P/M
+        const V* twom = TW_s;
+        const int per_t = a.ncp * L;
+        for (int idx = tid; idx < tb * per_t; idx += nth) {
+            const int t = idx / per_t;
+            const int r = idx - t * per_t;
+            const int cs = r / L;
+            const int qa = r - cs * L;
+            const V* Sp = S_s + t * KK + (qa + L - 1) * K;
+            const V* Sm = S_s + t * KK + (L - 1 - qa) * K;
+            V Xp = Sp[L - 1], Xm = Sm[L - 1];
+            V Yp = vmk<V>(0, 0), Ym = vmk<V>(0, 0);
+            for (int k = 1; k < a.N; ++k) {
+                const V tw = twom[(k - 1) * a.ncp + cs];
+                const V a1 = Sp[L - 1 + k], a2 = Sp[L - 1 - k];
+                const V b1 = Sm[L - 1 + k], b2 = Sm[L - 1 - k];
+                Xp.x += (a1.x + a2.x) * tw.x; Xp.y += (a1.y + a2.y) * tw.x;
+                Yp.x += (a1.x - a2.x) * tw.y; Yp.y += (a1.y - a2.y) * tw.y;
+                Xm.x += (b1.x + b2.x) * tw.x; Xm.y += (b1.y + b2.y) * tw.x;
+                Ym.x += (b1.x - b2.x) * tw.y; Ym.y += (b1.y - b2.y) * tw.y;
+            }
+            Yp = vmul_mi(Yp);
+            Ym = vmul_mi(Ym);
+            const int c1 = cs;
+            int c2 = a.n_omega - cs;
+            if (cs == 0 || c2 == cs) c2 = -1;
+            for (int side = 0; side < 2; ++side) {
+                const int c = side == 0 ? c1 : c2;
+                if (c < 0) break;
+                const V Up = side == 0 ? vadd(Xp, Yp) : vsub(Xp, Yp);
+                V* P = PM_s + (c * tb + t) * PMS;
+                V* M = P + PW;
+                if (qa == 0) {
+                    P[0] = Up;
+                    M[0] = vmk<V>(0, 0);
+                    for (int k = L; k < PW; ++k) { P[k] = vmk<V>(0, 0); M[k] = vmk<V>(0, 0); }
+                } else {
+                    const V Um = side == 0 ? vadd(Xm, Ym) : vsub(Xm, Ym);
+                    P[qa] = vadd(Up, Um);
+                    M[qa] = vmul_mi(vsub(Up, Um));
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     if constexpr (LH <= 8) {
         // stage 3: phi synthesis and store.  Wave w takes rows w, w + nwaves, ...; a lane
@@ -432,6 +423,12 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
     synth_block<T, LH, NS>(a, (int)blockIdx.x);
 }
 
+// The phi stage and store alone, from the staged path's P/M rows (L_h above 16).
+template <typename T, int LH>
+__global__ void __launch_bounds__(256) synth_pm_kernel(const SynthArgs a) {
+    synth_block<T, LH, 1, true>(a, (int)blockIdx.x);
+}
+
 // Several transforms that share one kernel instance in one grid (a tile list across
 // requests): transform r owns blocks [first[r], first[r+1]).  The per-transform arguments
 // travel in the kernel-argument block, so a launch needs no device allocation or copy.
@@ -448,12 +445,14 @@ static size_t synth_xsize(const DevPlan& P, int tb) {
     const int LH = lh_bucket(P.d.L_h);
     const int PW = LH <= 8 ? LH : (P.d.L_h + 3) / 4 * 4;
     const size_t rows = ((size_t)tb * P.d.n_omega + 7) / 8 * 8;
+    if (P.staged) return rows * (2 * PW + 1);             // P/M rows only
     return std::max((size_t)2 * P.d.L_h * P.d.L_h, rows * (2 * PW + 1));
 }
 
 static size_t synth_lds_bytes(const DevPlan& P, int tb) {
     const int L = P.d.L_h, K = 2 * L - 1;
     const size_t v = P.d.precision == SLSHT_FP64 ? 16 : 8;
+    if (P.staged) return synth_xsize(P, tb) * v;
     const size_t s = (size_t)tb * K * K;
     const size_t tw = (size_t)(L > 1 ? L - 1 : 0) * (P.d.n_omega / 2 + 1);
     return (s + synth_xsize(P, tb) + tw) * v;
@@ -490,7 +489,16 @@ static const void* synth_fn_t(int nslot, bool batch) {
     }
 }
 
+static const void* synth_pm_fn(const DevPlan& P) {
+    const bool f64 = P.d.precision == SLSHT_FP64;
+    switch (lh_bucket(P.d.L_h)) {
+        case 24: return f64 ? (const void*)synth_pm_kernel<double, 24> : (const void*)synth_pm_kernel<float, 24>;
+        default: return f64 ? (const void*)synth_pm_kernel<double, 32> : (const void*)synth_pm_kernel<float, 32>;
+    }
+}
+
 static const void* synth_fn(const DevPlan& P, bool batch = false) {
+    if (P.staged) return synth_pm_fn(P);
     const bool f64 = P.d.precision == SLSHT_FP64;
     const int ns = P.nslot_phi;
     switch (lh_bucket(P.d.L_h)) {
@@ -502,7 +510,9 @@ static const void* synth_fn(const DevPlan& P, bool batch = false) {
     }
 }
 
-const void* synthesis_kernel_key(const DevPlan& P) { return synth_fn(P); }
+// Staged plans run their own launches (W table, U GEMM, phi stage per chunk), so each one
+// gets a key of its own and is never grouped with other transforms.
+const void* synthesis_kernel_key(const DevPlan& P) { return P.staged ? (const void*)&P : synth_fn(P); }
 
 // Theta rows per block: stages 1-2 run between barriers with no stores in flight, so
 // the store stream is kept busy by other resident blocks.  The tile is the largest one
@@ -551,11 +561,30 @@ static SynthArgs synth_args(const DevPlan& P, const double2* A, const double2* h
     a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     a.xsize = (int)synth_xsize(P, P.tb);
     a.N = n_az_of(P.d);
+    a.item0 = 0;
+    a.pm = nullptr;
+    a.pm_ncw = 0;
     return a;
+}
+
+hipError_t launch_synthesis_pm(const DevPlan& P, const void* pm, int item0, int n, void* g,
+                               hipStream_t s) {
+    SynthArgs a = synth_args(P, nullptr, nullptr, g);
+    a.item0 = item0;
+    a.pm = pm;
+    a.pm_ncw = P.sg.ncw;
+    const int64_t nblk = (int64_t)n * a.n_tiles;
+    if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const void* fn = synth_pm_fn(P);
+    if (P.lds_bytes > 64 * 1024)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+    void* args[] = {&a};
+    return hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(P.block), args, P.lds_bytes, s);
 }
 
 hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h, void* g,
                             hipStream_t s) {
+    if (P.staged) return launch_synthesis_staged(P, A, h, g, s);
     SynthArgs a = synth_args(P, A, h, g);
     const int64_t nblk = (int64_t)P.n_items * a.n_tiles;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;   // grid.x limit
@@ -566,6 +595,11 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
 hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const* A,
                                   const double2* const* h, void* const* g, int n, hipStream_t s) {
     if (n < 1 || n > kSynthBatchMax) return hipErrorInvalidValue;
+    if (P[0]->staged) {
+        // staged plans are grouped alone (their key is unique)
+        if (n != 1) return hipErrorInvalidValue;
+        return launch_synthesis_staged(*P[0], A[0], h[0], g[0], s);
+    }
     const void* fn = synth_fn(*P[0], true);
     SynthBatch b;
     std::memset(&b, 0, sizeof(b));

@@ -37,7 +37,7 @@ def mid_case():
 def _full_case(L_f, L_h, l_lo, l_hi, n_phi, n_omega, prec, seed, **kw):
     rng = np.random.default_rng(seed)
     f = draw_coefficients(rng, L_f, 0.0)
-    h = draw_window(rng, L_h)
+    h = draw_window(rng, L_h, n_az=kw.get("n_az", 0))     # steerable: |r| >= n_az zeroed
     n_theta = (n_phi + 1) // 2
     plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, precision=prec,
                                   **kw))
@@ -202,4 +202,45 @@ def test_largest_phi_grid_sampled(L_h, prec, tol):
     ref = oracle_g_grid(f, h, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega,
                         idx + np.array([0, tlo, 0]))
     errs = per_l_rel_err(gather_rho(g, idx), ref, l_lo, l_hi, axis=1)
+    assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+@pytest.mark.parametrize("case", [
+    dict(L_f=7, L_h=20, l_lo=0, l_hi=9, n_phi=45, n_omega=39),                  # staged path
+    dict(L_f=6, L_h=18, l_lo=2, l_hi=8, n_phi=35, n_omega=5, n_az=3),           # steerable
+    dict(L_f=5, L_h=17, l_lo=0, l_hi=6, n_phi=33, n_omega=33, real_pair=True),  # L_h = 17
+])
+def test_staged_synthesis_whole_grid(case, prec, tol):
+    """Band-limits above 16 take the staged FULL path (W table, U GEMM over the items, phi
+    stage from the stored P/M rows): whole grid against the oracle, with a steerable window
+    and with the real-pair path."""
+    announce(f"staged whole grid {case} {prec}")
+    f, h, g, ref = _full_case(**case, prec=prec, seed=41)
+    errs = per_l_rel_err(g, ref, case["l_lo"], case["l_hi"])
+    assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_staged_synthesis_several_chunks_sampled(prec, tol):
+    """L_f = 64, L_h = 32, l in [80, 95) (2625 items, 191 x 96 x 63 grid): the P/M rows of
+    all items exceed the staged path's 4 GiB chunk, so the U GEMM and the phi stage run in
+    2 (FP32) or 4 (FP64) chunks of items; seeded rotations against the oracle, including
+    the first and last item of every chunk's neighbourhood."""
+    announce(f"staged chunks {prec}")
+    rng = np.random.default_rng(43)
+    L_f, L_h, l_lo, l_hi, n_phi, n_omega = 64, 32, 80, 95, 191, 63
+    n_theta = (n_phi + 1) // 2
+    f = draw_coefficients(rng, L_f, 2.0, True)
+    h = draw_window(rng, L_h)
+    plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, precision=prec))
+    g = plan.forward(dev(f), dev(h))
+    idx = np.stack([rng.integers(0, n_phi, 24), rng.integers(0, n_theta, 24),
+                    rng.integers(0, n_omega, 24)], 1)
+    idx[0] = (0, 0, 0)
+    idx[1] = (n_phi - 1, n_theta - 1, n_omega - 1)
+    ref = oracle_g_grid(f, h, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, idx)
+    errs = per_l_rel_err(gather_rho(g, idx), ref, l_lo, l_hi, axis=1)
+    del g
+    torch.cuda.empty_cache()
     assert max(errs.values()) <= tol, errs
