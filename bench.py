@@ -414,16 +414,52 @@ def serving_leg(n, rate):
     reqs = serving_stream(n, rate_hz=rate, seed=7)
     inputs = [r.inputs() for r in reqs]
     tot = sum(r.samples for r in reqs)
+    # per precision, the in-stream result of a request with the largest band-limits (the
+    # lowest l-window among them, to keep the copy small) is kept on the device and checked
+    # against the oracle on seeded rotations after the run
+    check = {}
+    for prec in ("fp64", "fp32"):
+        cand = [i for i, r in enumerate(reqs) if r.precision == prec]
+        if cand:
+            check[prec] = max(cand, key=lambda i: (reqs[i].L_f, reqs[i].L_h, -reqs[i].l_lo))
     srv = Server(hbm_budget=200 << 30, n_streams=4)
-    res = run_stream(srv, reqs, inputs=inputs)
+    res = run_stream(srv, reqs, inputs=inputs, keep=lambda i: i in check.values(),
+                     keep_on_device=True)
     srv.close()
     lat = res["latency_s"] * 1e3
+    sub = res["submit_s"] * 1e3
     out = {"requests": n, "arrival_rate_hz": rate, "hbm_budget_bytes": 200 << 30,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "mean_ms": float(lat.mean()), "value": tot / res["span_s"], "unit": "samples/s",
-           "span_s": res["span_s"], "samples": tot, "peak_budget_used_bytes": res["peak_used_bytes"]}
+           "span_s": res["span_s"], "samples": tot, "peak_budget_used_bytes": res["peak_used_bytes"],
+           "submit_p50_ms": float(np.percentile(sub, 50)),
+           "submit_p99_ms": float(np.percentile(sub, 99)),
+           "submit_max_ms": float(sub.max())}
+    errs = {}
+    for prec, i in check.items():
+        r = reqs[i]
+        f, h = inputs[i]
+        n_phi, n_theta, n_omega = r.grid
+        rng = np.random.default_rng(100 + i)
+        idx = np.stack([rng.integers(0, n_phi, 24), rng.integers(0, n_theta, 24),
+                        rng.integers(0, n_omega, 24)], 1)
+        from oracle.slsht import oracle_g_grid
+        ref = oracle_g_grid(f, h, r.L_f, r.L_h, r.l_lo, r.l_hi, n_phi, n_theta, n_omega, idx)
+        g = res["kept"][i].reshape(-1, n_omega, n_theta, n_phi)
+        sel = g[:, torch.as_tensor(idx[:, 2], device=g.device),
+                torch.as_tensor(idx[:, 1], device=g.device),
+                torch.as_tensor(idx[:, 0], device=g.device)].transpose(0, 1).cpu().numpy()
+        per_l = rel_err_per_l(sel, ref, r.l_lo, r.l_hi)
+        errs[prec] = {"request": i, "L_f": r.L_f, "L_h": r.L_h, "l_range": [r.l_lo, r.l_hi],
+                      "rotations": len(idx), "max_rel_frobenius_per_l": max(per_l),
+                      "max_abs": float(np.abs(sel - ref).max()),
+                      "max_abs_rel_to_max": float(np.abs(sel - ref).max() / np.abs(ref).max())}
+    res["kept"].clear()
+    out["error_vs_oracle"] = errs
     log(f"serving: {n} req at {rate}/s: p50 {out['p50_ms']:.2f} ms, p99 {out['p99_ms']:.2f} ms, "
-        f"{out['value']:.3e} samples/s")
+        f"{out['value']:.3e} samples/s; submit p50 {out['submit_p50_ms']:.3f} ms, "
+        f"p99 {out['submit_p99_ms']:.3f} ms; errors "
+        + ", ".join(f"{p} {e['max_rel_frobenius_per_l']:.2e}" for p, e in errs.items()))
     return out
 
 

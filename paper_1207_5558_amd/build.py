@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslsht.so")
 SOURCES = ["slsht_kernels.hip", "slsht_synth.hip", "slsht_energy.hip", "slsht_slepian.hip",
            "slsht_factored.hip", "slsht_modsht.hip", "slsht_noalloc.hip", "slsht_staged.hip",
-           "slsht_api.cpp", "slsht_server.cpp"]
+           "slsht_geom.cpp", "slsht_api.cpp", "slsht_server.cpp"]
 
 
 def hipcc() -> str:

@@ -39,7 +39,6 @@ namespace slsht {
 namespace {
 
 constexpr int kUWaves = 8;        // E2: one 16-row tile per wave
-constexpr int kPhiWaves = 8;      // E3
 
 // MFMA k-steps (2 complex degrees each) of the p-sum of U_{+-k}.
 __host__ __device__ inline int u_steps(int L, int k) { return (L - k + 1) / 2; }
@@ -51,65 +50,6 @@ __device__ inline f4v mfma4(float a, float b, f4v c) {
 }
 
 }  // namespace
-
-bool energy_geom(const slsht_desc& d, int n_theta_out, size_t lds_limit, EnergyGeom& g) {
-    g = EnergyGeom{};
-    g.L = d.L_h;
-    g.K = 2 * d.L_h - 1;
-    g.KP = (d.L_h + 3) / 4 * 4;
-    g.nkk = g.KP / 4;
-    g.N = n_az_of(d);
-    g.n_phi = d.n_phi;
-    g.n_omega = d.n_omega;
-    const int nct = (d.n_omega + 15) / 16;
-    g.nctp = nct == 3 ? 4 : nct;                       // omega tiles padded to divide 8 waves
-    g.ncw = g.nctp * 16;
-    g.nslot = (d.n_phi + 1) / 2;
-    g.nst = (g.nslot + 15) / 16;
-    g.n_theta_out = n_theta_out;
-    g.theta_lo = d.theta_lo;
-    g.l_lo = d.l_lo;
-    g.n_l = d.l_hi - d.l_lo;
-    g.real_pair = (d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
-    // E3: the block's twiddle fragments live in LDS; split the slot tiles over several
-    // blocks when one (l, theta) row's table does not fit
-    const size_t per_tile = (size_t)g.nkk * 64 * sizeof(float2);
-    const int fit = (int)std::min<size_t>(lds_limit / per_tile, (size_t)g.nst);
-    if (fit < 1) return false;
-    g.nsplit = (g.nst + fit - 1) / fit;
-    g.nstb = (g.nst + g.nsplit - 1) / g.nsplit;
-    g.per = kPhiWaves / g.nctp;
-    const int tpw = (g.nstb + g.per - 1) / g.per;
-    if (tpw > kEnergyMaxTpw) return false;
-    g.tpw = tpw <= 4 ? 4 : (tpw <= 8 ? 8 : (tpw <= 12 ? 12 : kEnergyMaxTpw));   // kernel bucket
-    g.slab = (int64_t)g.nctp * g.nkk * 64 * 4;
-    // orders per chunk: the P/M slabs of one chunk within the workspace budget
-    const int max_orders = g.real_pair ? d.l_hi : 2 * d.l_hi - 1;
-    const size_t per_order = (size_t)g.n_l * n_theta_out * g.slab * sizeof(float);
-    int mc = (int)std::max<size_t>(1, std::min<size_t>(kEnergyChunkBudget / per_order,
-                                                       (size_t)max_orders));
-    g.nchunks = (max_orders + mc - 1) / mc;
-    g.mc = (max_orders + g.nchunks - 1) / g.nchunks;
-    g.rows = g.n_l * g.mc;
-    g.ntiles = (g.rows + 15) / 16;
-    int steps = 0;
-    for (int k = 0; k < g.L; ++k) steps += (k ? 2 : 1) * u_steps(g.L, k);
-    g.afrag_tile = steps * 64;
-    auto al = [](size_t n) { return (n + 255) / 256 * 256; };
-    size_t off = 0;
-    g.off_w = off;
-    off += al((size_t)n_theta_out * g.L * g.L * g.ncw * sizeof(float2));
-    g.off_af = off;
-    off += al((size_t)g.ntiles * g.afrag_tile * sizeof(float));
-    g.off_pm = off;
-    off += al((size_t)g.rows * n_theta_out * g.slab * sizeof(float));
-    g.off_ep = off;
-    if (g.nchunks > 1)
-        off += al((size_t)g.n_l * n_theta_out * g.nsplit * kPhiWaves * g.tpw * 8 * 64 *
-                  sizeof(float));
-    g.total = off;
-    return true;
-}
 
 // ------------------------------------------------------------------------------
 // E1: the chunk's coupling rows in A-fragment order.  Row r of the chunk is degree
@@ -292,7 +232,7 @@ __global__ void __launch_bounds__(64 * kUWaves) energy_u_kernel(const float2* __
 // k-step), then E(a) += |C + S|^2, E(n - a) += |C - S|^2.  The energies stay in registers
 // over the chunk; between chunks they go to the partial buffer in register order.
 template <int TPW, int NKK>
-__global__ void __launch_bounds__(64 * kPhiWaves) energy_phi_kernel(
+__global__ void __launch_bounds__(64 * kEnergyPhiWaves) energy_phi_kernel(
     const float* __restrict__ pm, const float2* __restrict__ twf, float* __restrict__ ep,
     float* __restrict__ E, const EnergyGeom g, int chunk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -318,7 +258,7 @@ __global__ void __launch_bounds__(64 * kPhiWaves) energy_phi_kernel(
 
     float Ep[TPW][4], Em[TPW][4];
     float4* epb = reinterpret_cast<float4*>(ep) +
-                  ((int64_t)blockIdx.x * kPhiWaves + wave) * TPW * 2 * 64 + lane;
+                  ((int64_t)blockIdx.x * kEnergyPhiWaves + wave) * TPW * 2 * 64 + lane;
     if (first) {
 #pragma unroll
         for (int j = 0; j < TPW; ++j)
@@ -444,29 +384,6 @@ __global__ void __launch_bounds__(64 * kPhiWaves) energy_phi_kernel(
     }
 }
 
-// Twiddle fragments of E3 (host): entry (st, kk, lane) = (cos, sin)(2 pi (k a mod n_phi) / n_phi),
-// k = 4 kk + lane / 16, a = 16 st + lane % 16; zero for a >= nslot.  Phases reduced in integers.
-void energy_twiddles(const EnergyGeom& g, std::vector<float>& out) {
-    out.assign((size_t)g.nst * g.nkk * 64 * 2, 0.0f);
-    for (int st = 0; st < g.nst; ++st)
-        for (int kk = 0; kk < g.nkk; ++kk)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int k = 4 * kk + lane / 16, a = 16 * st + lane % 16;
-                if (a >= g.nslot) continue;
-                const long long r = ((long long)k * a) % g.n_phi;
-                const double ang = 2.0 * M_PI * (double)r / (double)g.n_phi;
-                const size_t i = (((size_t)st * g.nkk + kk) * 64 + lane) * 2;
-                out[i] = (float)std::cos(ang);
-                out[i + 1] = (float)std::sin(ang);
-            }
-}
-
-size_t energy_twiddle_bytes(const EnergyGeom& g) { return (size_t)g.nst * g.nkk * 64 * sizeof(float2); }
-
-size_t energy_lds_for(const DevPlan& P) {
-    return (size_t)P.eg.nstb * P.eg.nkk * 64 * sizeof(float2);
-}
-
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
                          hipStream_t s) {
     const EnergyGeom& g = P.eg;
@@ -504,7 +421,7 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
                            (const float2*)W, (const float*)af, pm, g, c);
         const float* pmc = pm;
         void* args[] = {(void*)&pmc, (void*)&twf, (void*)&ep, (void*)&E, (void*)&g, (void*)&c};
-        e = hipLaunchKernel(phi, pgrid, dim3(64 * kPhiWaves), args, lds_phi, s);
+        e = hipLaunchKernel(phi, pgrid, dim3(64 * kEnergyPhiWaves), args, lds_phi, s);
         if (e != hipSuccess) return e;
         e = hipGetLastError();
         if (e != hipSuccess) return e;

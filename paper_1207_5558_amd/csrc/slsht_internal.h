@@ -188,6 +188,7 @@ size_t energy_lds_for(const DevPlan& P);
 constexpr int kEnergyMaxOmega = 64;
 constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 waves, 17 each
 constexpr int kEnergyMaxTpw = 17;
+constexpr int kEnergyPhiWaves = 8;    // waves of one phi-stage block
 // Workspace budget of the P/M slabs of one chunk of orders.
 constexpr size_t kEnergyChunkBudget = (size_t)16 << 30;
 // Workspace budget of the P/M rows of one chunk of items (staged FULL path).

@@ -298,47 +298,6 @@ __global__ void __launch_bounds__(64 * kStagedWaves) staged_u_kernel(
 // ------------------------------------------------------------------------------
 // Host: geometry and launches.
 
-bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& g) {
-    g = StagedGeom{};
-    // Above band-limit 16 the theta stage (sum_p (2p+1)^2 complex MACs per theta row and item,
-    // 4.3e4 at L_h = 32) outweighs the phi stage and stores it feeds; at 16 and below the fused
-    // kernel hides it behind other blocks' stores and stays faster (measured at L_h = 16,
-    // L_f = 32..192: 4-16% in favour of the fused kernel; at L_h = 18..32: 8-32% for this path).
-    if (d.output_mode != SLSHT_OUT_FULL || d.L_h <= 16 || d.n_omega > kEnergyMaxOmega) return false;
-    g.L = d.L_h;
-    g.N = n_az_of(d);
-    g.PW = (d.L_h + 3) / 4 * 4;
-    g.n_omega = d.n_omega;
-    g.ncw = (d.n_omega + 15) / 16 * 16;
-    g.n_theta_out = n_theta_out;
-    g.l_lo = d.l_lo;
-    g.real_pair = (d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
-    g.f64 = d.precision == SLSHT_FP64 ? 1 : 0;
-    g.n_items = n_items;
-    const size_t vb = g.f64 ? 16 : 8, rb = g.f64 ? 8 : 4;
-    g.pm_item = (int64_t)n_theta_out * 2 * g.PW * g.ncw;
-    const size_t per_item = (size_t)g.pm_item * vb;
-    const size_t fit = std::max<size_t>(16, kStagedChunkBudget / per_item / 16 * 16);
-    g.nchunks = (int)(((size_t)n_items + fit - 1) / fit);
-    g.ichunk = (n_items + g.nchunks - 1) / g.nchunks;
-    g.ichunk = (g.ichunk + 15) / 16 * 16;
-    g.nchunks = (n_items + g.ichunk - 1) / g.ichunk;
-    g.ntiles = g.ichunk / 16;
-    int steps = 0;
-    for (int k = 0; k < g.L; ++k) steps += (k ? 2 : 1) * u_steps(g.L, k);
-    g.afrag_tile = steps * 64;
-    auto al = [](size_t n) { return (n + 255) / 256 * 256; };
-    size_t off = 0;
-    g.off_w = off;
-    off += al((size_t)n_theta_out * g.L * g.L * g.ncw * vb);
-    g.off_af = off;
-    off += al((size_t)g.ntiles * g.afrag_tile * rb);
-    g.off_pm = off;
-    off += al((size_t)g.ichunk * per_item);
-    g.total = off;
-    return true;
-}
-
 hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const double2* h, void* g,
                                    hipStream_t s) {
     const StagedGeom& sg = P.sg;

@@ -18,16 +18,21 @@ from .api import make_desc
 _hip = None
 
 
-def _hip_memcpy_d2h(dst: np.ndarray, src_ptr: int, nbytes: int) -> None:
-    """Device-to-host copy of a server result through the HIP runtime."""
+def _hip_memcpy(dst_ptr: int, src_ptr: int, nbytes: int, kind: int) -> None:
+    """hipMemcpy through the HIP runtime (kind 2: device to host, 3: device to device)."""
     global _hip
     if _hip is None:
         _hip = ctypes.CDLL("libamdhip64.so")
         _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
         _hip.hipMemcpy.restype = ctypes.c_int
-    rc = _hip.hipMemcpy(dst.ctypes.data, ctypes.c_void_p(src_ptr), nbytes, 2)  # DeviceToHost
+    rc = _hip.hipMemcpy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nbytes, kind)
     if rc != 0:
         raise RuntimeError(f"hipMemcpy failed with {rc}")
+
+
+def _hip_memcpy_d2h(dst: np.ndarray, src_ptr: int, nbytes: int) -> None:
+    """Device-to-host copy of a server result."""
+    _hip_memcpy(dst.ctypes.data, src_ptr, nbytes, 2)
 
 
 class Server:
@@ -76,6 +81,18 @@ class Server:
         _hip_memcpy_d2h(out, ptr, n)
         return out
 
+    def result_device(self, ticket: int, dtype, device: int = 0):
+        """Device copy (a torch tensor) of a finished request's output, flat."""
+        import torch
+        st, ptr, n, err = self.poll(ticket)
+        if st != L.REQ_DONE:
+            raise RuntimeError(f"ticket {ticket} not done (state {st}, err {err})")
+        out = torch.empty(n // torch.empty((), dtype=dtype).element_size(), dtype=dtype,
+                          device=f"cuda:{device}")
+        torch.cuda.synchronize(device)
+        _hip_memcpy(out.data_ptr(), ptr, n, 3)
+        return out
+
     def release(self, ticket: int) -> None:
         L.check(L.lib().slsht_release(self._h, ticket))
 
@@ -102,14 +119,18 @@ def request_desc(req) -> L.Desc:
                      precision=req.precision)
 
 
-def run_stream(server: Server, requests, inputs=None, keep=None, poll_sleep_s: float = 2e-4):
+def run_stream(server: Server, requests, inputs=None, keep=None, poll_sleep_s: float = 2e-4,
+               keep_on_device: bool = False):
     """Submit `requests` (ServingRequest list, sorted by arrival) at their arrival times
     and drive them to completion.  `inputs[i]` = (f, h) or None to draw from the request's
-    seed; `keep(i)` -> True to copy that result out.  Returns a dict with per-request
-    latencies (s), the results kept, the peak budget use seen, and the wall span."""
+    seed; `keep(i)` -> True to copy that result out (to the host, or with `keep_on_device`
+    into a torch device tensor, which holds the polling loop up far less).  Returns a dict
+    with per-request latencies (s), the host time of each slsht_submit call (s), the
+    results kept, the peak budget use seen, and the wall span."""
     n = len(requests)
     tickets = [None] * n
     lat = np.full(n, np.nan)
+    submit_s = np.full(n, np.nan)
     kept = {}
     peak = 0
     start = time.perf_counter()
@@ -121,7 +142,9 @@ def run_stream(server: Server, requests, inputs=None, keep=None, poll_sleep_s: f
         now = time.perf_counter() - start
         while i < n and requests[i].arrival_s <= now:
             f, h = inputs[i] if inputs is not None else requests[i].inputs()
+            ts_ = time.perf_counter()
             tickets[i] = server.submit(request_desc(requests[i]), f, h)
+            submit_s[i] = time.perf_counter() - ts_
             pending.append(i)
             i += 1
         still = []
@@ -135,8 +158,14 @@ def run_stream(server: Server, requests, inputs=None, keep=None, poll_sleep_s: f
                 lat[j] = td - (t0_srv + requests[j].arrival_s) if td > 0 else np.nan
                 lat[j] = max(lat[j], td - ts)
                 if keep is not None and keep(j):
-                    dt = np.complex128 if requests[j].precision == "fp64" else np.complex64
-                    kept[j] = server.result(tickets[j], dt)
+                    fp64 = requests[j].precision == "fp64"
+                    if keep_on_device:
+                        import torch
+                        kept[j] = server.result_device(
+                            tickets[j], torch.complex128 if fp64 else torch.complex64)
+                    else:
+                        kept[j] = server.result(tickets[j],
+                                                np.complex128 if fp64 else np.complex64)
                 server.release(tickets[j])
                 done += 1
             else:
@@ -150,4 +179,4 @@ def run_stream(server: Server, requests, inputs=None, keep=None, poll_sleep_s: f
             time.sleep(poll_sleep_s)
     span = time.perf_counter() - start
     return {"latency_s": lat, "kept": kept, "peak_used_bytes": peak, "span_s": span,
-            "tickets": tickets}
+            "tickets": tickets, "submit_s": submit_s}

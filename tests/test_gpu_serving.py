@@ -125,3 +125,53 @@ def test_energy_requests_and_error_paths():
         srv.submit(bad, f, h)
     assert e.value.status == L.SLSHT_EINVAL
     srv.close()
+
+
+def test_serving_shapes_in_a_queued_mix():
+    """The serving workload's shapes, including L_f = 192 with L_h = 16 in FP64 and FP32,
+    submitted at once into a budget below their total (12 GiB for ~33 GB of outputs), so
+    that admission queues: every result equals the same transform run alone (compared on
+    the device), and the two L_f = 192, L_h = 16 results match the oracle on sampled
+    rotations."""
+    announce("serving shapes in a queued mix")
+    shapes = [(192, 16, 0, 8, "fp64"), (192, 16, 8, 16, "fp32"), (128, 8, 40, 48, "fp64"),
+              (96, 16, 20, 28, "fp32"), (64, 4, 56, 64, "fp64"), (32, 16, 24, 32, "fp32"),
+              (192, 8, 30, 38, "fp32"), (128, 16, 0, 8, "fp64"), (160, 4, 100, 108, "fp64"),
+              (32, 8, 0, 8, "fp32")]
+    reqs = [ServingRequest(0.0, L_f, L_h, lo, hi, prec, 3000 + i)
+            for i, (L_f, L_h, lo, hi, prec) in enumerate(shapes)]
+    inputs = [r.inputs() for r in reqs]
+    total = sum(api.footprint(request_desc(r))[1] for r in reqs)
+    budget = 12 << 30
+    assert total > budget
+    srv = Server(hbm_budget=budget, n_streams=4)
+    tickets = [srv.submit(request_desc(r), f, h) for r, (f, h) in zip(reqs, inputs)]
+    queued = srv.stats()[2]
+    for i, t in enumerate(tickets):
+        srv.wait(t, 120000)
+        r = reqs[i]
+        dt = torch.complex128 if r.precision == "fp64" else torch.complex64
+        got = srv.result_device(t, dt)
+        srv.release(t)
+        n_phi, n_theta, n_omega = r.grid
+        f, h = inputs[i]
+        plan = api.Plan(api.make_desc(r.L_f, r.L_h, r.l_lo, r.l_hi, n_phi, n_theta, n_omega,
+                                      precision=r.precision))
+        alone = plan.forward(dev(f), dev(h)).reshape(-1)
+        assert torch.equal(got, alone), (i, shapes[i])
+        if i < 2:
+            rng = np.random.default_rng(50 + i)
+            idx = np.stack([rng.integers(0, n_phi, 30), rng.integers(0, n_theta, 30),
+                            rng.integers(0, n_omega, 30)], 1)
+            ref = oracle_g_grid(f, h, r.L_f, r.L_h, r.l_lo, r.l_hi, n_phi, n_theta, n_omega, idx)
+            g = got.reshape(-1, n_omega, n_theta, n_phi)
+            a = torch.as_tensor(idx[:, 0], device=g.device)
+            b = torch.as_tensor(idx[:, 1], device=g.device)
+            c = torch.as_tensor(idx[:, 2], device=g.device)
+            sample = g[:, c, b, a].transpose(0, 1).cpu().numpy()
+            tol = FP64_TOL if r.precision == "fp64" else FP32_TOL
+            assert np.linalg.norm(sample - ref) / np.linalg.norm(ref) <= tol, i
+        del got, alone, plan
+        torch.cuda.empty_cache()
+    srv.close()
+    assert queued > 0
