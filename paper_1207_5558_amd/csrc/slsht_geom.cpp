@@ -103,14 +103,14 @@ size_t energy_lds_for(const DevPlan& P) {
 
 bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& g) {
     g = StagedGeom{};
-    // Above band-limit 16 the theta stage (sum_p (2p+1)^2 complex MACs per theta row and item,
-    // 4.3e4 at L_h = 32) outweighs the phi stage and stores it feeds; at 16 and below the fused
-    // kernel hides it behind other blocks' stores and stays faster (measured at L_h = 16,
-    // L_f = 32..192: 4-16% in favour of the fused kernel; at L_h = 18..32: 8-32% for this path).
-    if (d.output_mode != SLSHT_OUT_FULL || d.L_h <= 16 || d.n_omega > kEnergyMaxOmega) return false;
+    // At window band-limits up to 16 the fused kernel of slsht_synth.hip (theta stage on the
+    // VALU, beside other blocks' phi stages on the matrix cores) is faster (measured at
+    // L_h = 16, L_f = 128 and 192: by 5-24%, FP64 and FP32).  Above 16 its theta stage
+    // (sum_p (2p+1)^2 complex MACs per theta row and item) outweighs the rest, and this path
+    // is ahead (the minimal grid of L_h = 18: 9.6 against 13.4 ms FP64).
+    if (d.output_mode != SLSHT_OUT_FULL || d.L_h <= 16 || d.n_omega > kWtableMaxOmega) return false;
     g.L = d.L_h;
     g.N = n_az_of(d);
-    g.PW = (d.L_h + 3) / 4 * 4;
     g.n_omega = d.n_omega;
     g.ncw = (d.n_omega + 15) / 16 * 16;
     g.n_theta_out = n_theta_out;
@@ -118,26 +118,29 @@ bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& 
     g.real_pair = (d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     g.f64 = d.precision == SLSHT_FP64 ? 1 : 0;
     g.n_items = n_items;
-    const size_t vb = g.f64 ? 16 : 8, rb = g.f64 ? 8 : 4;
-    g.pm_item = (int64_t)n_theta_out * 2 * g.PW * g.ncw;
-    const size_t per_item = (size_t)g.pm_item * vb;
-    const size_t fit = std::max<size_t>(16, kStagedChunkBudget / per_item / 16 * 16);
-    g.nchunks = (int)(((size_t)n_items + fit - 1) / fit);
-    g.ichunk = (n_items + g.nchunks - 1) / g.nchunks;
-    g.ichunk = (g.ichunk + 15) / 16 * 16;
-    g.nchunks = (n_items + g.ichunk - 1) / g.ichunk;
-    g.ntiles = g.ichunk / 16;
+    g.ntiles = (n_items + 15) / 16;
     int steps = 0;
     for (int k = 0; k < g.L; ++k) steps += (k ? 2 : 1) * u_steps(g.L, k);
     g.afrag_tile = steps * 64;
+    const size_t vb = g.f64 ? 16 : 8, rb = g.f64 ? 8 : 4;
+    // block: `it` items x 16 omega columns; its P|M rows (2L + 1 complex each) sit in LDS
+    g.it = (g.f64 || g.L > 24) ? 8 : 16;
+    g.lds = (size_t)g.it * 16 * (2 * g.L + 1) * vb;
+    g.threads = g.lds > 80 * 1024 ? 512 : 256;
+    g.n_itiles = ((n_items + g.it - 1) / g.it + 7) / 8 * 8;
+    g.n_ctiles = g.ncw / 16;
+    // theta rows per block: as many as keep >= 4096 blocks in the grid
+    const int64_t units = (int64_t)g.n_itiles * g.n_ctiles;
+    int tc = (int)std::max<int64_t>(1, units * n_theta_out / 4096);
+    tc = std::min(tc, std::max(1, n_theta_out));
+    g.n_tchunks = (n_theta_out + tc - 1) / tc;
+    g.tchunk = (n_theta_out + g.n_tchunks - 1) / g.n_tchunks;
     auto al = [](size_t n) { return (n + 255) / 256 * 256; };
     size_t off = 0;
     g.off_w = off;
     off += al((size_t)n_theta_out * g.L * g.L * g.ncw * vb);
     g.off_af = off;
     off += al((size_t)g.ntiles * g.afrag_tile * rb);
-    g.off_pm = off;
-    off += al((size_t)g.ichunk * per_item);
     g.total = off;
     return true;
 }

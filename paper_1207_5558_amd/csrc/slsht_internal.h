@@ -60,12 +60,16 @@ struct EnergyGeom {
 // Geometry of the staged FULL synthesis (slsht_staged.hip; window band-limits above 16,
 // n_omega <= 64): U GEMM over chunks of items, then the phi stage from the P/M rows.
 struct StagedGeom {
-    int L, N, PW, n_omega, ncw;      // band-limit, n_az, L rounded up to 4, omega (padded)
+    int L, N, n_omega, ncw;          // band-limit, n_az, omega (padded to 16s)
     int n_theta_out, l_lo, real_pair, f64;
-    int n_items, ichunk, nchunks, ntiles;   // items, items per chunk (16s), chunks, tiles
+    int n_items, ntiles;             // items, 16-item tiles of the A fragments
     int afrag_tile;                  // elements of A fragments per 16-item tile
-    int64_t pm_item;                 // complex elements of P/M rows per item
-    size_t off_w, off_af, off_pm, total;   // workspace byte offsets and size
+    int it;                          // items per block of the W/U kernel (16 or 8)
+    int n_itiles, n_ctiles;          // item tiles (rounded up to 8s), 16-column omega tiles
+    int tchunk, n_tchunks;           // theta rows per block, theta chunks
+    int threads;                     // threads per block
+    size_t lds;                      // LDS bytes per block
+    size_t off_w, off_af, total;     // workspace byte offsets and size
 };
 
 // Everything a launch needs for one descriptor.
@@ -164,13 +168,11 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
 // (w64) or complex64 as [theta][wq_off(q) + p - |q|][ncw].
 hipError_t launch_wtable(const void* dtab, bool d64, const double2* h, void* W, bool w64, int L,
                          int N, int n_omega, int ncw, int n_theta_out, hipStream_t s);
-// Staged FULL synthesis: geometry (false if the plan does not qualify) and launch.
+// FULL synthesis through the W table and the U GEMM (W/U kernel): geometry (false if the
+// plan does not qualify) and launch.
 bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& g);
 hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const double2* h, void* g,
                                    hipStream_t s);
-// Phi stage + store of the FULL kernel from P/M rows of items [item0, item0 + n).
-hipError_t launch_synthesis_pm(const DevPlan& P, const void* pm, int item0, int n, void* g,
-                               hipStream_t s);
 // Workspace bytes of a plan view (ENERGY or staged FULL; 0 otherwise).
 size_t plan_workspace_bytes(const DevPlan& P);
 // Host-only: geometry of the ENERGY path for d (false if no tiling fits lds_limit).
@@ -186,13 +188,13 @@ size_t energy_lds_for(const DevPlan& P);
 
 // ENERGY output limits of the MFMA kernels (checked on the host).
 constexpr int kEnergyMaxOmega = 64;
+// omega samples of the W table (its twiddles sit in 16 KB of LDS beside the h d rows)
+constexpr int kWtableMaxOmega = 1024;
 constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 waves, 17 each
 constexpr int kEnergyMaxTpw = 17;
 constexpr int kEnergyPhiWaves = 8;    // waves of one phi-stage block
 // Workspace budget of the P/M slabs of one chunk of orders.
 constexpr size_t kEnergyChunkBudget = (size_t)16 << 30;
-// Workspace budget of the P/M rows of one chunk of items (staged FULL path).
-constexpr size_t kStagedChunkBudget = (size_t)4 << 30;
 
 }  // namespace slsht
 

@@ -1,5 +1,5 @@
-// gfx950 kernels of the staged FULL synthesis (window band-limits above 16, n_omega <= 64),
-// and the W table it shares with the ENERGY path.
+// gfx950 kernels of the W/U FULL synthesis (window band-limits above 8), and the W table it
+// shares with the ENERGY path.
 //
 // The separated form (eq. Eq:alternative_harmonic_formulation_wigner, separation of
 // variables of Section IV-B) is summed with the q'-sum first:
@@ -9,15 +9,14 @@
 // W depends on neither l nor m, so the p-sum is a dense product over the (l, m) items for
 // each (theta_b, q): a GEMM on the matrix cores (v_mfma_f64_16x16x4f64 for FP64 plans,
 // v_mfma_f32_16x16x4f32 for FP32-mixed).  Kernels:
-//   wtable_kernel      W of every theta row (FP64 sums; stored in the plan precision)
-//   staged_afrag_kernel A^p_{+-k} of a chunk of items in MFMA A-fragment order
-//   staged_u_kernel    U, the fold into P_k, M_k, stored per (item, theta row) as rows
-//                      [P_0 .. P_{PW-1}, M_0 .. M_{PW-1}] x omega
-// and the phi synthesis + store of the FULL kernel reads those rows (synth_pm_kernel in
-// slsht_synth.hip) in place of its own theta and omega stages.
+//   wtable_kernel       W of every theta row (FP64 sums; stored in the plan precision)
+//   staged_afrag_kernel A^p_{+-k} of the items in MFMA A-fragment order
+//   wu_phi_kernel       per block of items, omega columns and theta rows: U, the fold into
+//                       P_k, M_k in LDS, then the phi stage and store (slsht_phi.h)
 // MFMA lane layouts (gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16]; the FP32 form
 // returns D rows 4(l/16)+r, the FP64 form rows (l/16)+4r, of column l%16.
 #include "slsht_device.h"
+#include "slsht_phi.h"
 
 #include <hip/hip_runtime.h>
 
@@ -27,9 +26,6 @@
 namespace slsht {
 
 namespace {
-
-constexpr int kStagedWaves = 8;        // u kernel: one 16-item tile per wave
-constexpr int kStagedCols = 64;        // u kernel: omega columns per block (4 tiles of 16)
 
 // MFMA step and D-row map per precision.
 template <typename T> struct StagedMfma;
@@ -64,7 +60,7 @@ __global__ void __launch_bounds__(256) wtable_kernel(const double2* __restrict__
                                                      OV* __restrict__ W, int L, int N,
                                                      int n_omega, int ncw) {
     __shared__ double2 hd[SLSHT_MAX_LH * (2 * SLSHT_MAX_LH - 1)];
-    __shared__ double2 tw[kEnergyMaxOmega];
+    extern __shared__ double2 tw[];                      // [n_omega] (dynamic)
     const int K = 2 * L - 1;
     const int t = blockIdx.x, qi = blockIdx.y;
     const int k = (qi + 1) / 2;
@@ -114,15 +110,17 @@ __global__ void __launch_bounds__(256) wtable_kernel(const double2* __restrict__
 
 hipError_t launch_wtable(const void* dtab, bool d64, const double2* h, void* W, bool w64, int L,
                          int N, int n_omega, int ncw, int n_theta_out, hipStream_t s) {
+    if (n_omega < 1 || n_omega > kWtableMaxOmega) return hipErrorInvalidValue;
     const dim3 grid(n_theta_out, 2 * L - 1), block(256);
+    const size_t lds = (size_t)n_omega * sizeof(double2);
     if (d64 && w64)
-        hipLaunchKernelGGL((wtable_kernel<double, double2>), grid, block, 0, s, h,
+        hipLaunchKernelGGL((wtable_kernel<double, double2>), grid, block, lds, s, h,
                            (const double*)dtab, (double2*)W, L, N, n_omega, ncw);
     else if (d64)
-        hipLaunchKernelGGL((wtable_kernel<double, float2>), grid, block, 0, s, h,
+        hipLaunchKernelGGL((wtable_kernel<double, float2>), grid, block, lds, s, h,
                            (const double*)dtab, (float2*)W, L, N, n_omega, ncw);
     else
-        hipLaunchKernelGGL((wtable_kernel<float, float2>), grid, block, 0, s, h,
+        hipLaunchKernelGGL((wtable_kernel<float, float2>), grid, block, lds, s, h,
                            (const float*)dtab, (float2*)W, L, N, n_omega, ncw);
     return hipGetLastError();
 }
@@ -162,141 +160,179 @@ __global__ void __launch_bounds__(64) staged_afrag_kernel(const double2* __restr
 }
 
 // ------------------------------------------------------------------------------
-// U_{+-k}(theta_b, omega_c) for 16 items per wave and 64 omega columns per block, as complex
-// GEMMs on real MFMAs (complex inner index p expanded to (Re, Im), B = [[W_re, W_im],
-// [-W_im, W_re]] row pairs), folded in registers and stored to the P/M rows of the chunk:
-//   pm[((item - item0) n_theta_out + theta) 2PW ncw + kslot ncw + c],  kslot = k (P_k) or
-//   PW + k (M_k); rows k = L .. PW-1 are zero.
-// W_{+-k} of the block's theta row and column range is staged in LDS; the next k's W rows
-// and A fragments are loaded into registers while this k's MFMAs run.
-template <typename T>
-__global__ void __launch_bounds__(64 * kStagedWaves) staged_u_kernel(
+// The W/U kernel: one block = `IT` items x 16 omega columns x a run of theta rows.  Per
+// theta row:
+//   1. U_{+-k}(theta, omega_c) for the block's items and columns, as complex GEMMs on real
+//      MFMAs (the complex inner index p expanded to (Re, Im), B = [[W_re, W_im],
+//      [-W_im, W_re]] row pairs); the waves split the k, and each folds its U_{+-k} into
+//      P_k = U_k + U_{-k}, M_k = -i (U_k - U_{-k}) and writes them to the block's P|M rows
+//      in LDS (row = item * 16 + column: P_0..P_{L-1} at 0, M_0..M_{L-1} at L);
+//   2. the phi stage over those rows on the matrix cores (phi_stage_mfma), stored to g.
+// With IT = 8 the A operand's rows 8..15 are zero and the D rows past 8 are dropped (FP64
+// and L_h > 24, whose P|M rows would not leave room in LDS for two blocks per CU).
+// Blocks are laid out so that those sharing an item tile (the same A fragments) run on one
+// XCD: block b goes to XCD b mod 8 under round-robin dispatch.
+struct WUArgs {
+    int L, n_omega, ncw, n_theta_out, n_phi, nslot, l_lo, real_pair, n_items;
+    int afrag_tile, n_itiles, n_ctiles, tchunk, n_tchunks;
+};
+
+// offset (in 64-lane fragment steps) of U_{+k}'s A fragments within a 16-item tile
+__device__ __forceinline__ int afrag_off(int L, int k) {
+    int off = 0;
+    for (int j = 0; j < k; ++j) off += (j ? 2 : 1) * u_steps(L, j);
+    return off;
+}
+
+template <typename T, int LH>
+__global__ void __launch_bounds__(512) wu_phi_kernel(
     const typename VecOf<T>::type* __restrict__ W, const T* __restrict__ af,
-    typename VecOf<T>::type* __restrict__ pm, const StagedGeom g, int n_chunk) {
+    const typename VecOf<T>::type* __restrict__ twphi, typename VecOf<T>::type* __restrict__ g,
+    const WUArgs a) {
     using V = typename VecOf<T>::type;
     using MF = StagedMfma<T>;
     using Acc = typename MF::acc;
+    constexpr int IT = (sizeof(T) == 8 || LH > 24) ? 8 : 16;
+    constexpr int SB = 4;                            // MFMA steps per load group of the U GEMM
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    V* Ws = reinterpret_cast<V*>(smem_raw);               // [<= max(L, 2L-2) rows][64]
-    const int L = g.L, ncw = g.ncw;
-    const int t = blockIdx.x, c0 = blockIdx.z * kStagedCols;
-    const int ncols = min(kStagedCols, ncw - c0);          // a multiple of 16
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.y * kStagedWaves + wave;
-    const int ntiles = (n_chunk + 15) / 16;
-    const bool active = tile < ntiles;
-    const int j4 = lane >> 4, col = lane & 15;
-    const V* Wt = W + (int64_t)t * L * L * ncw + c0;
-    const T* aft = af + (int64_t)(active ? tile : 0) * g.afrag_tile + lane;
-    const int64_t rowlen = (int64_t)2 * g.PW * ncw;        // V elements per (item, theta)
+    V* PM_s = reinterpret_cast<V*>(smem_raw);        // [IT * 16 rows][2L + 1]
+    __shared__ int64_t s_lm[IT], s_mir[IT];
+    __shared__ T s_sign[IT];
 
-    int64_t base[4];
-    bool rv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = tile * 16 + MF::drow(j4, r);
-        rv[r] = active && row < n_chunk;
-        base[r] = ((int64_t)row * g.n_theta_out + t) * rowlen + c0 + col;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, j = b >> 3;
+    const int n_inner = a.n_ctiles * a.n_tchunks;
+    const int grp = j / n_inner;
+    const int itile = grp * 8 + xcd;
+    const int inner = j - grp * n_inner;
+    const int ctile = inner % a.n_ctiles;
+    const int tch = inner / a.n_ctiles;
+    const int item0 = itile * IT;
+    if (item0 >= a.n_items) return;                  // whole block: uniform
+    const int L = a.L, pms = 2 * L + 1, ncw = a.ncw;
+    const int c0 = ctile * 16;
+    const int t_begin = tch * a.tchunk, t_end = min(a.n_theta_out, t_begin + a.tchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int i16 = lane & 15, j4 = lane >> 4;
+
+    const int64_t lm_stride = (int64_t)a.n_omega * a.n_theta_out * a.n_phi;
+    if (tid < IT) {
+        const int item = item0 + tid;
+        if (item < a.n_items) {
+            const Item it = item_decode(item, a.l_lo, a.real_pair);
+            s_lm[tid] = (int64_t)it.lm * lm_stride;
+            s_mir[tid] = it.mirror >= 0 ? (int64_t)it.mirror * lm_stride : -1;
+            s_sign[tid] = (it.m & 1) ? T(-1) : T(1);
+        } else {
+            s_lm[tid] = -1;
+            s_mir[tid] = -1;
+            s_sign[tid] = T(1);
+        }
     }
+    // this lane's A-operand row: item (item0 % 16) + i16 of its 16-item fragment tile
+    const bool arow = i16 < IT && item0 + i16 < a.n_items;
+    const T* aft = af + (int64_t)(item0 / 16) * a.afrag_tile + j4 * 16 + (item0 % 16) + i16;
+    __syncthreads();
 
-    // W rows of the next k in registers (at most (2L-2) x 64 elements over the block)
-    constexpr int kWPer = ((2 * SLSHT_MAX_LH - 2) * kStagedCols + 64 * kStagedWaves - 1) /
-                          (64 * kStagedWaves);
-    V wr[kWPer];
-    auto load_w = [&](int k) {
-        const int n = (k ? 2 * (L - k) : L) * ncols;
-        const V* src = Wt + (int64_t)wq_off(L, k) * ncw;
-#pragma unroll
-        for (int i = 0; i < kWPer; ++i) {
-            const int idx = threadIdx.x + i * 64 * kStagedWaves;
-            const int r = idx / ncols, c = idx - r * ncols;
-            wr[i] = idx < n ? src[(int64_t)r * ncw + c] : vmk<V>(0, 0);
-        }
-    };
-    // FP64: the A fragments are loaded at their own k (register budget)
-    constexpr bool kPrefetchA = sizeof(T) == 4;
-    T apn[16], amn[16];
-    auto load_a = [&](int k, int off) {
-        const int steps = u_steps(L, k);
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            apn[s] = (active && s < steps) ? aft[(int64_t)(off + s) * 64] : T(0);
-            amn[s] = (active && k && s < steps) ? aft[(int64_t)(off + steps + s) * 64] : T(0);
-        }
-    };
-    load_w(0);
-    if (kPrefetchA) load_a(0, 0);
-    int aoff = 0;
-    for (int k = 0; k < L; ++k) {
-        const int steps = u_steps(L, k);
-        __syncthreads();
-        {
-            const int n = (k ? 2 * (L - k) : L) * ncols;
-#pragma unroll
-            for (int i = 0; i < kWPer; ++i) {
-                const int idx = threadIdx.x + i * 64 * kStagedWaves;
-                const int r = idx / ncols, c = idx - r * ncols;
-                if (idx < n) Ws[r * kStagedCols + c] = wr[i];
-            }
-        }
-        __syncthreads();
-        if (!kPrefetchA) load_a(k, aoff);
-        T ap[16], am[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            ap[s] = apn[s];
-            am[s] = amn[s];
-        }
-        const int aoff_next = aoff + (k ? 2 : 1) * steps;
-        if (k + 1 < L) {
-            load_w(k + 1);
-            if (kPrefetchA) load_a(k + 1, aoff_next);
-        }
-        if (active) {
+    for (int t = t_begin; t < t_end; ++t) {
+        const V* Wt = W + (int64_t)t * L * L * ncw + c0 + i16;
+        for (int k = wave; k < L; k += nw) {
+            const int steps = u_steps(L, k);
+            const int off = afrag_off(L, k);
             const int lastp = L - k - 1;
-            for (int ct = 0; ct < ncols / 16; ++ct) {
-                Acc upr = {0, 0, 0, 0}, upi = {0, 0, 0, 0}, umr = {0, 0, 0, 0}, umi = {0, 0, 0, 0};
-                const V* wcol = Ws + ct * 16 + col;
+            const V* wpk = Wt + (int64_t)wq_off(L, k) * ncw;
+            const V* wmk = wpk + (int64_t)(L - k) * ncw;
+            Acc upr = {0, 0, 0, 0}, upi = {0, 0, 0, 0}, umr = {0, 0, 0, 0}, umi = {0, 0, 0, 0};
+            // the p-sum in groups of SB MFMA steps: loads of a group first, then its MFMAs
+            for (int s0 = 0; s0 < steps; s0 += SB) {
+                T ap[SB], am[SB];
+                V wp[SB], wm[SB];
 #pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    if (s >= steps) break;
+                for (int u = 0; u < SB; ++u) {
+                    const int s = s0 + u;
                     // rows past the last degree meet a zero A fragment; clamp them in range
                     const int rp = min(2 * s + (j4 >> 1), lastp);
-                    const V wp = wcol[rp * kStagedCols];
-                    upr = MF::step(ap[s], (j4 & 1) ? -wp.y : wp.x, upr);
-                    upi = MF::step(ap[s], (j4 & 1) ? wp.x : wp.y, upi);
+                    const bool in = s < steps;
+                    ap[u] = (in && arow) ? aft[(int64_t)(off + s) * 64] : T(0);
+                    am[u] = (in && arow && k) ? aft[(int64_t)(off + steps + s) * 64] : T(0);
+                    wp[u] = in ? wpk[(int64_t)rp * ncw] : vmk<V>(0, 0);
+                    wm[u] = (in && k) ? wmk[(int64_t)rp * ncw] : vmk<V>(0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    upr = MF::step(ap[u], (j4 & 1) ? -wp[u].y : wp[u].x, upr);
+                    upi = MF::step(ap[u], (j4 & 1) ? wp[u].x : wp[u].y, upi);
                     if (k) {
-                        const V wm = wcol[(L - k + rp) * kStagedCols];
-                        umr = MF::step(am[s], (j4 & 1) ? -wm.y : wm.x, umr);
-                        umi = MF::step(am[s], (j4 & 1) ? wm.x : wm.y, umi);
+                        umr = MF::step(am[u], (j4 & 1) ? -wm[u].y : wm[u].x, umr);
+                        umi = MF::step(am[u], (j4 & 1) ? wm[u].x : wm[u].y, umi);
                     }
                 }
+            }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (!rv[r]) continue;
-                    V* o = pm + base[r] + ct * 16;
-                    o[(int64_t)k * ncw] = vmk<V>(upr[r] + umr[r], upi[r] + umi[r]);
-                    o[(int64_t)(g.PW + k) * ncw] =
-                        k ? vmk<V>(upi[r] - umi[r], umr[r] - upr[r]) : vmk<V>(0, 0);   // M_0 = 0
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int item = MF::drow(j4, r);
+                if (item >= IT) continue;
+                V* row = PM_s + (item * 16 + i16) * pms;
+                row[k] = vmk<V>(upr[r] + umr[r], upi[r] + umi[r]);
+                row[L + k] = k ? vmk<V>(upi[r] - umi[r], umr[r] - upr[r]) : vmk<V>(0, 0);  // M_0 = 0
             }
         }
-        aoff = aoff_next;
+        __syncthreads();
+        const int n_theta = a.n_theta_out, n_phi = a.n_phi, n_omega = a.n_omega;
+        phi_stage_mfma<T, LH>(PM_s, pms, L, IT * 16, L, twphi, a.nslot, n_phi,
+                              [&](int rr, V*& out, V*& mout, T& ms) {
+                                  const int item = rr >> 4, c = c0 + (rr & 15);
+                                  const int64_t base = s_lm[item];
+                                  if (base < 0 || c >= n_omega) {
+                                      out = nullptr;
+                                      mout = nullptr;
+                                      ms = T(1);
+                                      return;
+                                  }
+                                  const int64_t rowoff = ((int64_t)c * n_theta + t) * n_phi;
+                                  out = g + base + rowoff;
+                                  const int64_t mb = s_mir[item];
+                                  mout = mb >= 0 ? g + mb + rowoff : nullptr;
+                                  ms = s_sign[item];
+                              });
+        __syncthreads();
     }
-    // rows k = L .. PW-1 of P and M are zero (the phi stage runs whole k-steps)
-    for (int k = L; k < g.PW; ++k)
-        for (int ct = 0; ct < ncols / 16; ++ct)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (rv[r]) {
-                    V* o = pm + base[r] + ct * 16;
-                    o[(int64_t)k * ncw] = vmk<V>(0, 0);
-                    o[(int64_t)(g.PW + k) * ncw] = vmk<V>(0, 0);
-                }
 }
 
 // ------------------------------------------------------------------------------
-// Host: geometry and launches.
+// Host: launches.
+
+template <typename T, int LH>
+static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* W, const void* af,
+                            void* g, hipStream_t s) {
+    using V = typename VecOf<T>::type;
+    WUArgs a;
+    a.L = sg.L;
+    a.n_omega = sg.n_omega;
+    a.ncw = sg.ncw;
+    a.n_theta_out = sg.n_theta_out;
+    a.n_phi = P.d.n_phi;
+    a.nslot = P.nslot_phi;
+    a.l_lo = sg.l_lo;
+    a.real_pair = sg.real_pair;
+    a.n_items = sg.n_items;
+    a.afrag_tile = sg.afrag_tile;
+    a.n_itiles = sg.n_itiles;
+    a.n_ctiles = sg.n_ctiles;
+    a.tchunk = sg.tchunk;
+    a.n_tchunks = sg.n_tchunks;
+    const int64_t nblk = (int64_t)sg.n_itiles * sg.n_ctiles * sg.n_tchunks;
+    if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const void* fn = (const void*)wu_phi_kernel<T, LH>;
+    if (sg.lds > 64 * 1024)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sg.lds);
+    const V* Wv = static_cast<const V*>(W);
+    const T* afv = static_cast<const T*>(af);
+    const V* tw = static_cast<const V*>(P.T->tw_phi);
+    V* gv = static_cast<V*>(g);
+    void* args[] = {(void*)&Wv, (void*)&afv, (void*)&tw, (void*)&gv, (void*)&a};
+    return hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(sg.threads), args, sg.lds, s);
+}
 
 hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const double2* h, void* g,
                                    hipStream_t s) {
@@ -305,35 +341,26 @@ hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const dou
     if (!ws) return hipErrorInvalidValue;
     void* W = ws + sg.off_w;
     void* af = ws + sg.off_af;
-    void* pm = ws + sg.off_pm;
     hipError_t e = launch_wtable(P.T->dtab, sg.f64 != 0, h, W, sg.f64 != 0, sg.L, sg.N,
                                  sg.n_omega, sg.ncw, sg.n_theta_out, s);
     if (e != hipSuccess) return e;
-    const size_t lds_u = (size_t)std::max(sg.L, 2 * (sg.L - 1)) * kStagedCols *
-                         (sg.f64 ? sizeof(double2) : sizeof(float2));
-    for (int c = 0; c < sg.nchunks; ++c) {
-        const int item0 = c * sg.ichunk;
-        const int n = std::min(sg.ichunk, sg.n_items - item0);
-        const int ntiles = (n + 15) / 16;
-        const dim3 ugrid(sg.n_theta_out, (ntiles + kStagedWaves - 1) / kStagedWaves,
-                         (sg.ncw + kStagedCols - 1) / kStagedCols);
-        if (sg.f64) {
-            hipLaunchKernelGGL(staged_afrag_kernel<double>, dim3(ntiles), dim3(64), 0, s, A,
-                               (double*)af, sg, item0, n);
-            hipLaunchKernelGGL(staged_u_kernel<double>, ugrid, dim3(64 * kStagedWaves), lds_u, s,
-                               (const double2*)W, (const double*)af, (double2*)pm, sg, n);
-        } else {
-            hipLaunchKernelGGL(staged_afrag_kernel<float>, dim3(ntiles), dim3(64), 0, s, A,
-                               (float*)af, sg, item0, n);
-            hipLaunchKernelGGL(staged_u_kernel<float>, ugrid, dim3(64 * kStagedWaves), lds_u, s,
-                               (const float2*)W, (const float*)af, (float2*)pm, sg, n);
-        }
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = launch_synthesis_pm(P, pm, item0, n, g, s);
-        if (e != hipSuccess) return e;
+    if (sg.f64)
+        hipLaunchKernelGGL(staged_afrag_kernel<double>, dim3(sg.ntiles), dim3(64), 0, s, A,
+                           (double*)af, sg, 0, sg.n_items);
+    else
+        hipLaunchKernelGGL(staged_afrag_kernel<float>, dim3(sg.ntiles), dim3(64), 0, s, A,
+                           (float*)af, sg, 0, sg.n_items);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int LH = sg.L <= 16 ? 16 : (sg.L <= 24 ? 24 : 32);
+    if (sg.f64) {
+        if (LH == 16) return launch_wu<double, 16>(sg, P, W, af, g, s);
+        if (LH == 24) return launch_wu<double, 24>(sg, P, W, af, g, s);
+        return launch_wu<double, 32>(sg, P, W, af, g, s);
     }
-    return hipSuccess;
+    if (LH == 16) return launch_wu<float, 16>(sg, P, W, af, g, s);
+    if (LH == 24) return launch_wu<float, 24>(sg, P, W, af, g, s);
+    return launch_wu<float, 32>(sg, P, W, af, g, s);
 }
 
 }  // namespace slsht
