@@ -124,7 +124,7 @@ bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& 
     g.afrag_tile = steps * 64;
     const size_t vb = g.f64 ? 16 : 8, rb = g.f64 ? 8 : 4;
     // block: `it` items x 16 omega columns; its P|M rows (2L + 1 complex each) sit in LDS
-    g.it = (g.f64 || g.L > 24) ? 8 : 16;
+    g.it = (size_t)16 * 16 * (2 * g.L + 1) * vb <= kWuMaxLds ? 16 : 8;
     g.lds = (size_t)g.it * 16 * (2 * g.L + 1) * vb;
     g.threads = g.lds > 80 * 1024 ? 512 : 256;
     g.n_itiles = ((n_items + g.it - 1) / g.it + 7) / 8 * 8;

@@ -190,6 +190,8 @@ size_t energy_lds_for(const DevPlan& P);
 constexpr int kEnergyMaxOmega = 64;
 // omega samples of the W table (its twiddles sit in 16 KB of LDS beside the h d rows)
 constexpr int kWtableMaxOmega = 1024;
+// LDS of one W/U block's P|M rows (the CU has 160 KB; a few hundred bytes stay static)
+constexpr size_t kWuMaxLds = (size_t)156 << 10;
 constexpr int kEnergyMaxTiles = 136;   // (slot tiles x omega tiles) over 8 waves, 17 each
 constexpr int kEnergyMaxTpw = 17;
 constexpr int kEnergyPhiWaves = 8;    // waves of one phi-stage block

@@ -168,8 +168,9 @@ __global__ void __launch_bounds__(64) staged_afrag_kernel(const double2* __restr
 //      P_k = U_k + U_{-k}, M_k = -i (U_k - U_{-k}) and writes them to the block's P|M rows
 //      in LDS (row = item * 16 + column: P_0..P_{L-1} at 0, M_0..M_{L-1} at L);
 //   2. the phi stage over those rows on the matrix cores (phi_stage_mfma), stored to g.
-// With IT = 8 the A operand's rows 8..15 are zero and the D rows past 8 are dropped (FP64
-// and L_h > 24, whose P|M rows would not leave room in LDS for two blocks per CU).
+// IT = 16 where the block's P|M rows fit in LDS (FP64 up to L_h = 19); else IT = 8: the A
+// operand's rows 8..15 are zero and the D rows past 8 are dropped.  Blocks whose P|M rows
+// take more than 80 KB run 8 waves (one block per CU), the others 4.
 // Blocks are laid out so that those sharing an item tile (the same A fragments) run on one
 // XCD: block b goes to XCD b mod 8 under round-robin dispatch.
 struct WUArgs {
@@ -184,7 +185,7 @@ __device__ __forceinline__ int afrag_off(int L, int k) {
     return off;
 }
 
-template <typename T, int LH>
+template <typename T, int LH, int IT>
 __global__ void __launch_bounds__(512) wu_phi_kernel(
     const typename VecOf<T>::type* __restrict__ W, const T* __restrict__ af,
     const typename VecOf<T>::type* __restrict__ twphi, typename VecOf<T>::type* __restrict__ g,
@@ -192,7 +193,6 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
     using V = typename VecOf<T>::type;
     using MF = StagedMfma<T>;
     using Acc = typename MF::acc;
-    constexpr int IT = (sizeof(T) == 8 || LH > 24) ? 8 : 16;
     constexpr int SB = 4;                            // MFMA steps per load group of the U GEMM
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* PM_s = reinterpret_cast<V*>(smem_raw);        // [IT * 16 rows][2L + 1]
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
 // ------------------------------------------------------------------------------
 // Host: launches.
 
-template <typename T, int LH>
+template <typename T, int LH, int IT>
 static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* W, const void* af,
                             void* g, hipStream_t s) {
     using V = typename VecOf<T>::type;
@@ -323,7 +323,7 @@ static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* 
     a.n_tchunks = sg.n_tchunks;
     const int64_t nblk = (int64_t)sg.n_itiles * sg.n_ctiles * sg.n_tchunks;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const void* fn = (const void*)wu_phi_kernel<T, LH>;
+    const void* fn = (const void*)wu_phi_kernel<T, LH, IT>;
     if (sg.lds > 64 * 1024)
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sg.lds);
     const V* Wv = static_cast<const V*>(W);
@@ -352,15 +352,15 @@ hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const dou
                            (float*)af, sg, 0, sg.n_items);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int LH = sg.L <= 16 ? 16 : (sg.L <= 24 ? 24 : 32);
+    // window band-limits 17..32 (staged_geom): buckets 24 and 32
+    const bool b24 = sg.L <= 24;
     if (sg.f64) {
-        if (LH == 16) return launch_wu<double, 16>(sg, P, W, af, g, s);
-        if (LH == 24) return launch_wu<double, 24>(sg, P, W, af, g, s);
-        return launch_wu<double, 32>(sg, P, W, af, g, s);
+        if (sg.it == 16) return launch_wu<double, 24, 16>(sg, P, W, af, g, s);   // L_h <= 19
+        return b24 ? launch_wu<double, 24, 8>(sg, P, W, af, g, s)
+                   : launch_wu<double, 32, 8>(sg, P, W, af, g, s);
     }
-    if (LH == 16) return launch_wu<float, 16>(sg, P, W, af, g, s);
-    if (LH == 24) return launch_wu<float, 24>(sg, P, W, af, g, s);
-    return launch_wu<float, 32>(sg, P, W, af, g, s);
+    return b24 ? launch_wu<float, 24, 16>(sg, P, W, af, g, s)
+               : launch_wu<float, 32, 16>(sg, P, W, af, g, s);
 }
 
 }  // namespace slsht
