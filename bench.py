@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "g(ρ;ℓ,m) samples/s on 1 MI355X, FP32-mixed vs FP64 at stated error; p99 ms"
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK = 157.3          # TFLOP/s, dense FP32 MFMA (MI355X spec sheet)
+MFMA_F64_PEAK = 78.6           # TFLOP/s, dense FP64 MFMA (MI355X spec sheet)
 KERNEL = "synth_full_kernel"
 
 
@@ -37,9 +38,9 @@ def log(msg):
 
 def kernel_source_digest() -> str:
     """Digest of the sources of the FULL synthesis kernel (its file and the device
-    helpers it includes); a counter summary is used only if it carries the same one."""
+    headers it includes); a counter summary is used only if it carries the same one."""
     h = hashlib.sha256()
-    for name in ("slsht_synth.hip", "slsht_device.h"):
+    for name in ("slsht_synth.hip", "slsht_device.h", "slsht_phi.h"):
         h.update(open(os.path.join(ROOT, "paper_1207_5558_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -357,6 +358,15 @@ def factored_leg(torch, api, L_h=18, L_fs=(18, 34, 66, 130)):
             ach = gb / (res[ms_key] * 1e-3) / 1e9
             res[key] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": gb}
+        # the same synthesis against the FP64 matrix peak: per output row (l, m, theta, omega)
+        # the U GEMM takes sum_{|q|<L_h} (L_h - |q|) = L_h^2 complex MACs (8 flops each) and the
+        # folded phi sums L_h x (n_phi + 1)/2 slots x 8 flops
+        rows = plan.n_lm * L_h * K
+        flops = rows * (8 * L_h * L_h + 8 * L_h * ((K + 1) // 2))
+        tf = flops / (res["separated_synthesis_ms"] * 1e-3) / 1e12
+        res["roofline_separated_synthesis_mfma"] = {
+            "bound": "mfma", "achieved": tf, "peak": MFMA_F64_PEAK, "unit": "TFLOP/s",
+            "frac": tf / MFMA_F64_PEAK, "algorithmic_flops_per_launch": flops}
         out["points"].append({"L_f": L_f, "n_lm": plan.n_lm, **res})
         log(f"paper route L_f={L_f}: tau1 {res['tau1_ms']:.3f} ms, tau2 {res['tau2_ms']:.3f} ms, "
             f"tau3 {res['tau3_ms']:.3f} ms | 3j coupling {res['coupling_3j_ms']:.3f} ms, "
@@ -485,6 +495,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the steerable-window, several-window and Slepian-window legs")
+    ap.add_argument("--legs", default="steerable,windows,slepian,factored,lh16",
+                    help="comma list of the NEXT / serving-shape legs to run (unless --no-next)")
     ap.add_argument("--serve-n", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, req/s")
     ap.add_argument("--serve-rate-sat", type=float, default=20000.0,
@@ -648,12 +660,18 @@ def main():
                                        "frac": alg32 / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
     if not args.no_next:
-        line["steerable_mid"] = steerable_leg(torch, api, args.steps, args.warmup)
-        line["windows_mid"] = windows_leg(torch, api, f_t, outputs["fp64"], args.steps,
-                                          args.warmup)
-        line["slepian_window"] = slepian_leg(api)
-        line["factored_route"] = factored_leg(torch, api)
-        line["full_lh16"] = full_lh16_leg(torch, api, 5, 2)
+        legs = set(x.strip() for x in args.legs.split(",") if x.strip())
+        if "steerable" in legs:
+            line["steerable_mid"] = steerable_leg(torch, api, args.steps, args.warmup)
+        if "windows" in legs:
+            line["windows_mid"] = windows_leg(torch, api, f_t, outputs["fp64"], args.steps,
+                                              args.warmup)
+        if "slepian" in legs:
+            line["slepian_window"] = slepian_leg(api)
+        if "factored" in legs:
+            line["factored_route"] = factored_leg(torch, api)
+        if "lh16" in legs:
+            line["full_lh16"] = full_lh16_leg(torch, api, 5, 2)
 
     # the mid-size outputs (17 GB) stay resident for the error check below; the other legs
     # fit beside them in 288 GB of HBM
