@@ -41,9 +41,9 @@
  *    never frees them and keeps no reference after a call returns.  A
  *    `stream` argument is a hipStream_t (NULL = the default stream); work is
  *    enqueued asynchronously on it.  slsht_forward, slsht_forward_batch,
- *    slsht_forward_windows and slsht_coupling enqueue kernels only (no
- *    allocation, memset or host synchronisation), so they may be captured in
- *    a HIP graph; slsht_inverse reads h_0^0 on the host and may not.
+ *    slsht_forward_windows, slsht_coupling, slsht_synthesize and slsht_inverse
+ *    enqueue kernels only (no allocation, memset or host synchronisation), so
+ *    they may be captured in a HIP graph.
  *  - Every function returns an slsht_status; nothing throws across the ABI.
  *    Argument checks run on the host before any launch.  The message of the
  *    last failure on the calling thread is available from slsht_last_error().
@@ -210,11 +210,13 @@ int slsht_forward_windows(slsht_plan_t plan, const void* f, const void* h, int n
  * f_out[lm] = f_hat / (sqrt(16 pi^3) h_0^0)  (eq. Eq:inversion_2).  The result is
  * f_l^m for l < L_f and zero (to rounding) for l >= L_f.
  *   g: device, FULL layout of this plan;  h: device complex128[L_h * L_h] (only
- *   h_0^0 is read, on the host, with a synchronous 16-byte copy);
+ *   h_0^0 is read, by the kernel);
  *   f_out: device complex128[l_hi^2 - l_lo^2].
- * Requires a FULL plan over all theta rows with n_phi >= 2 L_h - 1,
- * n_omega >= 2 n_az - 1 (n_az = L_h unless the window is steerable), and
- * h_0^0 != 0 (SLSHT_EINVAL otherwise).  Asynchronous after the h_0^0 read. */
+ * Requires a FULL plan over all theta rows with n_phi >= 2 L_h - 1 and
+ * n_omega >= 2 n_az - 1 (n_az = L_h unless the window is steerable)
+ * (SLSHT_EINVAL otherwise).  The inverse divides by h_0^0, which the library
+ * does not read on the host: h_0^0 = 0 gives non-finite f_out, not an error
+ * status.  Asynchronous on `stream`, kernels only. */
 int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, void* stream);
 
 /* The paper's own route, for comparison (factoring of rotations, Section IV-B):

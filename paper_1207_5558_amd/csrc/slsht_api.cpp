@@ -631,20 +631,10 @@ int slsht_inverse(slsht_plan_t plan, const void* g, const void* h, void* f_out, 
     DeviceGuard guard(plan->device);
     if (!guard.ok) return slsht::set_error(SLSHT_EDEVICE, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)stream;
-    double2 h00;
-    hipError_t e = hipMemcpyAsync(&h00, h, sizeof(double2), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "reading h_0^0");
-    const double mag2 = h00.x * h00.x + h00.y * h00.y;
-    if (!(mag2 > 0.0))
-        return slsht::set_error(SLSHT_EINVAL, "h_0^0 is zero: the inverse divides by it");
-    // scale = 1 / (n_phi^2 n_omega sqrt(16 pi^3) h00)
+    // f = f_hat / (sqrt(16 pi^3) h00) with f_hat = (1 / (n_phi^2 n_omega)) x the weighted sum
     const double k = 1.0 / ((double)P.d.n_phi * P.d.n_phi * P.d.n_omega *
                             std::sqrt(16.0 * M_PI * M_PI * M_PI));
-    double2 scale;
-    scale.x = k * h00.x / mag2;
-    scale.y = -k * h00.y / mag2;
-    e = slsht::launch_inverse(P, g, scale, (double2*)f_out, s);
+    hipError_t e = slsht::launch_inverse(P, g, k, (const double2*)h, (double2*)f_out, s);
     if (e != hipSuccess) return hip_fail(e, "inverse launch");
     return SLSHT_OK;
 }

@@ -180,8 +180,9 @@ bool energy_geom(const slsht_desc& d, int n_theta_out, size_t lds_limit, EnergyG
 // Twiddle fragments (cos, sin)(k phi_a) of the ENERGY phi stage, float pairs.
 void energy_twiddles(const EnergyGeom& g, std::vector<float>& out);
 size_t energy_twiddle_bytes(const EnergyGeom& g);
-hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,
-                          hipStream_t s);
+// f_out = k * (beta-weighted sum of g) / h[0], h_0^0 read on the device.
+hipError_t launch_inverse(const DevPlan& P, const void* g, double k, const double2* h,
+                          double2* f_out, hipStream_t s);
 // Chooses tb / block / lds_bytes of the FULL synthesis (host only).
 bool choose_synthesis_shape(DevPlan& P, size_t lds_limit);
 size_t energy_lds_for(const DevPlan& P);

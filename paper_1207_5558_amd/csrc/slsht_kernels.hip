@@ -291,7 +291,8 @@ hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipSt
 template <typename V>
 __global__ void __launch_bounds__(256) inverse_kernel(const V* __restrict__ g,
                                                       const double* __restrict__ qw, int n_phi,
-                                                      int n_theta, int n_omega, double2 scale,
+                                                      int n_theta, int n_omega, double k,
+                                                      const double2* __restrict__ h,
                                                       double2* __restrict__ f_out) {
     __shared__ double qs[(SLSHT_MAX_NPHI + 1) / 2];
     __shared__ double red[2][8];
@@ -316,22 +317,28 @@ __global__ void __launch_bounds__(256) inverse_kernel(const V* __restrict__ g,
     if (threadIdx.x == 0) {
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { sr += red[0][k]; si += red[1][k]; }
+        // f = k * sum / h_0^0 (read here, so that no host synchronisation is needed)
+        const double2 h00 = h[0];
+        const double mag2 = h00.x * h00.x + h00.y * h00.y;
+        const double scx = k * h00.x / mag2, scy = -k * h00.y / mag2;
         double2 o;
-        o.x = scale.x * sr - scale.y * si;
-        o.y = scale.x * si + scale.y * sr;
+        o.x = scx * sr - scy * si;
+        o.y = scx * si + scy * sr;
         f_out[blockIdx.x] = o;
     }
 }
 
-hipError_t launch_inverse(const DevPlan& P, const void* g, double2 scale, double2* f_out,
-                          hipStream_t s) {
+hipError_t launch_inverse(const DevPlan& P, const void* g, double k, const double2* h,
+                          double2* f_out, hipStream_t s) {
     const int n_lm = P.d.l_hi * P.d.l_hi - P.d.l_lo * P.d.l_lo;
     if (P.d.precision == SLSHT_FP64)
         hipLaunchKernelGGL(inverse_kernel<double2>, dim3(n_lm), dim3(256), 0, s,
-                           (const double2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
+                           (const double2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, k, h,
+                           f_out);
     else
         hipLaunchKernelGGL(inverse_kernel<float2>, dim3(n_lm), dim3(256), 0, s,
-                           (const float2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, scale, f_out);
+                           (const float2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, k, h,
+                           f_out);
     return hipGetLastError();
 }
 

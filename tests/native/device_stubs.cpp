@@ -42,7 +42,7 @@ hipError_t launch_synthesis_batch(const DevPlan* const*, const double2* const*, 
 hipError_t launch_energy(const DevPlan&, const double2*, const double2*, float*, hipStream_t) {
     return hipErrorNoDevice;
 }
-hipError_t launch_inverse(const DevPlan&, const void*, double2, double2*, hipStream_t) {
+hipError_t launch_inverse(const DevPlan&, const void*, double, const double2*, double2*, hipStream_t) {
     return hipErrorNoDevice;
 }
 

@@ -1,5 +1,5 @@
-"""The forward entry points enqueue only kernels (no allocation, no memset, no host
-synchronisation), so a caller can capture them in a HIP graph: every replay must equal
+"""The forward and inverse entry points enqueue only kernels (no allocation, no memset, no
+host synchronisation), so a caller can capture them in a HIP graph: every replay must equal
 the eager result bit for bit, with the program's own eager work and synchronisations
 between replays."""
 import numpy as np
@@ -47,6 +47,25 @@ def test_forward_graph_replays_equal_eager(prec):
     eager = plan.forward(ft, ht).clone()
     g = plan.empty_output()
     _replays_match(lambda s: plan.forward(ft, ht, g, stream=s), [g], [eager])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_and_inverse_graph_replays_equal_eager(prec):
+    """slsht_inverse reads h_0^0 in its kernel, so forward + inverse capture as one graph."""
+    announce(f"graph forward + inverse {prec}")
+    wl = workload("tiny")
+    f, h = make_inputs(wl)
+    plan = api.Plan(api.desc_for(wl, precision=prec))
+    ft, ht = dev(f), dev(h)
+    g_e = plan.forward(ft, ht)
+    f_e = plan.inverse(g_e, ht).clone()
+    g = plan.empty_output()
+    fo = torch.empty_like(f_e)
+
+    def step(s):
+        plan.forward(ft, ht, g, stream=s)
+        plan.inverse(g, ht, fo, stream=s)
+    _replays_match(step, [g, fo], [g_e, f_e])
 
 
 def test_energy_and_batch_graph_replays_equal_eager():

@@ -78,8 +78,8 @@ def test_inverse_argument_checks():
     g = plan.forward(dev(f), dev(h))
     h0 = h.copy()
     h0[0] = 0.0
-    with pytest.raises(L.SlshtError, match="h_0"):
-        plan.inverse(g, dev(h0))
+    # h_0^0 is read by the kernel (no host synchronisation): a zero gives non-finite output
+    assert not np.isfinite(plan.inverse(g, dev(h0)).cpu().numpy()).any()
     part = api.Plan(api.desc_for(wl, theta_lo=1))
     with pytest.raises(L.SlshtError, match="theta"):
         part.inverse(part.forward(dev(f), dev(h)), dev(h))
