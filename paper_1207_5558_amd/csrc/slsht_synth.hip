@@ -35,6 +35,7 @@ struct SynthArgs {
     void* g;
     int64_t dstride;
     int L, K, n_phi, n_omega, n_theta_out, tb, n_tiles, nslot, ncp, l_lo, real_pair;
+    int nblk;     // blocks of the transform (n_items x n_tiles)
     int N;        // azimuthal band-limit of the window (|q'| < N)
     int xsize;    // elements of the A/h | P/M union region in LDS
 };
@@ -227,9 +228,27 @@ __device__ __forceinline__ void synth_block(const SynthArgs& a, const int bid) {
     }
 }
 
+// Round-robin dispatch sends block b to XCD b mod 8.  For the VALU phi form the blocks are
+// renumbered so that each XCD runs one contiguous run of (item, theta tile) blocks:
+// neighbouring tiles of an item, which share the output lines at their boundaries, then go
+// through the same L2 (mid workload: 2.10 -> 1.97 ms FP64, 1.18 -> 1.04 ms FP32).  The MFMA
+// form keeps dispatch order (the same renumbering cost it 7% at L_h = 16, L_f = 192).  The
+// grid is a multiple of 8 blocks; those past the transform exit.
+template <int LH>
+__device__ __forceinline__ int xcd_block(int nblk_grid) {
+    if constexpr (LH <= 8) {
+        const int per = nblk_grid >> 3;
+        return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    } else {
+        return (int)blockIdx.x;
+    }
+}
+
 template <typename T, int LH, int NS>
 __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
-    synth_block<T, LH, NS>(a, (int)blockIdx.x);
+    const int bid = xcd_block<LH>((int)gridDim.x);
+    if (bid >= a.nblk) return;
+    synth_block<T, LH, NS>(a, bid);
 }
 
 // Several transforms that share one kernel instance in one grid (a tile list across
@@ -237,9 +256,11 @@ __global__ void __launch_bounds__(256) synth_full_kernel(const SynthArgs a) {
 // travel in the kernel-argument block, so a launch needs no device allocation or copy.
 template <typename T, int LH, int NS>
 __global__ void __launch_bounds__(256) synth_batch_kernel(const SynthBatch b) {
+    const int bid = xcd_block<LH>((int)gridDim.x);
+    if (bid >= b.first[b.n]) return;
     int r = 0;
-    while (r + 1 < b.n && (int)blockIdx.x >= b.first[r + 1]) ++r;
-    synth_block<T, LH, NS>(b.r[r], (int)blockIdx.x - b.first[r]);
+    while (r + 1 < b.n && bid >= b.first[r + 1]) ++r;
+    synth_block<T, LH, NS>(b.r[r], bid - b.first[r]);
 }
 
 static int lh_bucket(int L) { return L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 24 ? 24 : 32))); }
@@ -359,6 +380,7 @@ static SynthArgs synth_args(const DevPlan& P, const double2* A, const double2* h
     a.real_pair = (P.d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     a.xsize = (int)synth_xsize(P, P.tb);
     a.N = n_az_of(P.d);
+    a.nblk = (int)std::min<int64_t>((int64_t)P.n_items * a.n_tiles, 0x7fffffff);
     return a;
 }
 
@@ -367,9 +389,11 @@ hipError_t launch_synthesis(const DevPlan& P, const double2* A, const double2* h
     if (P.staged) return launch_synthesis_staged(P, A, h, g, s);
     SynthArgs a = synth_args(P, A, h, g);
     const int64_t nblk = (int64_t)P.n_items * a.n_tiles;
-    if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;   // grid.x limit
+    const int64_t grid = (nblk + 7) / 8 * 8;                         // 8 XCDs
+    if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;   // grid.x limit
+    a.nblk = (int)nblk;
     void* args[] = {&a};
-    return hipLaunchKernel(synth_fn(P), dim3((unsigned)nblk), dim3(P.block), args, P.lds_bytes, s);
+    return hipLaunchKernel(synth_fn(P), dim3((unsigned)grid), dim3(P.block), args, P.lds_bytes, s);
 }
 
 hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const* A,
@@ -396,10 +420,12 @@ hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const*
         lds = std::max(lds, P[i]->lds_bytes);
     }
     b.first[n] = (int)nblk;
+    const int64_t grid = (nblk + 7) / 8 * 8;                         // 8 XCDs
+    if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     void* args[] = {&b};
-    return hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(P[0]->block), args, lds, s);
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(P[0]->block), args, lds, s);
 }
 
 }  // namespace slsht
