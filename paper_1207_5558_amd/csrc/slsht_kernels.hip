@@ -293,13 +293,16 @@ __global__ void __launch_bounds__(256) inverse_kernel(const V* __restrict__ g,
                                                       const double* __restrict__ qw, int n_phi,
                                                       int n_theta, int n_omega, double k,
                                                       const double2* __restrict__ h,
-                                                      double2* __restrict__ f_out) {
+                                                      double2* __restrict__ f_out, int n_lm) {
+    // each XCD (block b runs on XCD b mod 8) takes a contiguous run of the (l, m) slabs
+    const int lm = (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+    if (lm >= n_lm) return;
     __shared__ double qs[(SLSHT_MAX_NPHI + 1) / 2];
     __shared__ double red[2][8];
     for (int i = threadIdx.x; i < n_theta; i += blockDim.x) qs[i] = qw[i];
     __syncthreads();
     const int64_t n = (int64_t)n_omega * n_theta * n_phi;
-    const V* gp = g + (int64_t)blockIdx.x * n;
+    const V* gp = g + (int64_t)lm * n;
     double ar = 0.0, ai = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const int b = (int)((i / n_phi) % n_theta);
@@ -324,21 +327,22 @@ __global__ void __launch_bounds__(256) inverse_kernel(const V* __restrict__ g,
         double2 o;
         o.x = scx * sr - scy * si;
         o.y = scx * si + scy * sr;
-        f_out[blockIdx.x] = o;
+        f_out[lm] = o;
     }
 }
 
 hipError_t launch_inverse(const DevPlan& P, const void* g, double k, const double2* h,
                           double2* f_out, hipStream_t s) {
     const int n_lm = P.d.l_hi * P.d.l_hi - P.d.l_lo * P.d.l_lo;
+    const int grid = (n_lm + 7) / 8 * 8;
     if (P.d.precision == SLSHT_FP64)
-        hipLaunchKernelGGL(inverse_kernel<double2>, dim3(n_lm), dim3(256), 0, s,
+        hipLaunchKernelGGL(inverse_kernel<double2>, dim3(grid), dim3(256), 0, s,
                            (const double2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, k, h,
-                           f_out);
+                           f_out, n_lm);
     else
-        hipLaunchKernelGGL(inverse_kernel<float2>, dim3(n_lm), dim3(256), 0, s,
+        hipLaunchKernelGGL(inverse_kernel<float2>, dim3(grid), dim3(256), 0, s,
                            (const float2*)g, P.T->qw, P.d.n_phi, P.d.n_theta, P.d.n_omega, k, h,
-                           f_out);
+                           f_out, n_lm);
     return hipGetLastError();
 }
 

@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
     const int xcd = b & 7, j = b >> 3;
     const int n_inner = a.n_ctiles * a.n_tchunks;
     const int grp = j / n_inner;
-    const int itile = grp * 8 + xcd;
+    const int itile = xcd * (a.n_itiles >> 3) + grp;
     const int inner = j - grp * n_inner;
     const int ctile = inner % a.n_ctiles;
     const int tch = inner / a.n_ctiles;
