@@ -313,7 +313,9 @@ int slsht_poll(slsht_server_t server, uint64_t ticket, int* state, const void** 
                size_t* out_bytes, int* err);
 /* Blocks until the request is DONE or FAILED (or timeout_ms elapses: EBUSY). */
 int slsht_wait(slsht_server_t server, uint64_t ticket, int timeout_ms);
-/* Returns a finished request's output memory to the budget. */
+/* Returns a finished request's output memory to the budget; the server may hand it to
+ * the next admitted request at once, so any work of the caller that reads *g_dev
+ * (copies, kernels, on any stream) must have completed before this call. */
 int slsht_release(slsht_server_t server, uint64_t ticket);
 /* Timestamps (seconds on the server's monotonic clock) of a finished request:
  * submit, admission (enqueue) and completion.  Any pointer may be NULL. */

@@ -82,7 +82,9 @@ class Server:
         return out
 
     def result_device(self, ticket: int, dtype, device: int = 0):
-        """Device copy (a torch tensor) of a finished request's output, flat."""
+        """Device copy (a torch tensor) of a finished request's output, flat.  Returns once
+        the copy has completed: a device-to-device hipMemcpy may return before it does, and
+        after `release` the server may hand the block to a new request at once."""
         import torch
         st, ptr, n, err = self.poll(ticket)
         if st != L.REQ_DONE:
@@ -91,6 +93,7 @@ class Server:
                           device=f"cuda:{device}")
         torch.cuda.synchronize(device)
         _hip_memcpy(out.data_ptr(), ptr, n, 3)
+        torch.cuda.synchronize(device)
         return out
 
     def release(self, ticket: int) -> None:

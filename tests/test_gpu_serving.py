@@ -175,3 +175,23 @@ def test_serving_shapes_in_a_queued_mix():
         torch.cuda.empty_cache()
     srv.close()
     assert queued > 0
+
+
+def test_device_copies_survive_immediate_reuse():
+    """A saturated stream whose blocks are reused as soon as they are released: results
+    copied out on the device (Server.result_device) must equal the same transform run alone,
+    i.e. the copy has completed before the ticket is released."""
+    announce("serving device copies under reuse")
+    reqs = serving_stream(300, rate_hz=1e5, seed=13, L_f_choices=(24, 32))
+    srv = Server(hbm_budget=3 << 30, n_streams=4)
+    keep = set(range(0, len(reqs), 3))
+    res = run_stream(srv, reqs, keep=lambda i: i in keep, keep_on_device=True)
+    srv.close()
+    for i in sorted(keep):
+        r = reqs[i]
+        f, h = r.inputs()
+        n_phi, n_theta, n_omega = r.grid
+        plan = api.Plan(api.make_desc(r.L_f, r.L_h, r.l_lo, r.l_hi, n_phi, n_theta, n_omega,
+                                      precision=r.precision))
+        alone = plan.forward(dev(f), dev(h)).reshape(-1)
+        assert torch.equal(res["kept"][i], alone), (i, r)
