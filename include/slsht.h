@@ -111,7 +111,7 @@ const char* slsht_last_error(void);
 int slsht_validate(const slsht_desc* desc);
 
 /* Host-only byte counts for a descriptor: device memory a plan holds
- * (Wigner-d table, twiddles, beta weights, coupling scratch, ENERGY workspace), the output
+ * (Wigner-d table, twiddles, beta weights, coupling scratch, synthesis workspace), the output
  * buffer slsht_forward writes, and per-call scratch.  Any pointer may be NULL.
  * Needs no GPU. */
 int slsht_footprint(const slsht_desc* desc, size_t* plan_bytes, size_t* out_bytes,
@@ -126,10 +126,11 @@ int64_t slsht_coupling_size(const slsht_desc* desc);
  * eq. Eq:Dlm) on the GPU in FP64 by the three-term recursion in p (stored in
  * FP32 for SLSHT_FP32_MIXED), the phi and omega twiddles, and the beta weights
  * q(theta_b) of the discrete inverse (Section IV-A).  The plan owns that memory,
- * a coupling scratch of slsht_coupling_size() complex doubles and, for ENERGY
- * plans, the workspace of the energy kernels (W table, P/M fragments of one chunk
- * of orders, partial energies; up to about 19 GiB, included in plan_bytes of
- * slsht_footprint).  Forward,
+ * a coupling scratch of slsht_coupling_size() complex doubles and a synthesis
+ * workspace: for ENERGY plans that of the energy kernels (W table, P/M fragments of
+ * one chunk of orders, partial energies; up to about 19 GiB), for FULL plans with
+ * L_h > 16 the W table and the coupling in MFMA fragment order; included in
+ * plan_bytes of slsht_footprint.  Forward,
  * coupling and inverse calls on one plan share that scratch: issue them on one
  * stream, or use one plan per stream.  The tables are built on a private stream
  * that is synchronised before return. */
@@ -177,8 +178,8 @@ int slsht_coupling(slsht_plan_t plan, const void* f, void* A, void* stream);
  *   A: device complex128[slsht_coupling_size()], layout of slsht_coupling;
  *   h, g: as for slsht_forward on this plan.
  * Lets a caller reuse one coupling for several windows, and time the synthesis
- * kernels by themselves.  Asynchronous on `stream`; ENERGY plans use the plan's
- * workspace, so calls on one plan are issued on one stream. */
+ * kernels by themselves.  Asynchronous on `stream`; ENERGY plans and FULL plans with
+ * L_h > 16 use the plan's workspace, so calls on one plan are issued on one stream. */
 int slsht_synthesize(slsht_plan_t plan, const void* A, const void* h, void* g, void* stream);
 
 /* Several forward transforms in few launches (continuous batching, Section IV-B's
