@@ -86,7 +86,7 @@ struct DevPlan {
     int block = 256;                // threads per synthesis block
     size_t lds_bytes = 0;           // dynamic LDS of the synthesis kernel
     EnergyGeom eg{};                // ENERGY plans: tiles, chunks, workspace layout
-    bool staged = false;            // FULL plans synthesised by the staged path
+    bool staged = false;            // FULL plans synthesised by the W/U path (slsht_staged.hip)
     StagedGeom sg{};                // staged FULL plans: chunks, workspace layout
     void* ework = nullptr;          // ENERGY / staged plans: workspace of
                                     // workspace_bytes(*this) bytes

@@ -6,8 +6,9 @@
 // twiddles) cached by the fields they depend on, builds plan views, and enqueues each group
 // on the next of the server's streams: input copies, couplings, then one synthesis grid for
 // FULL requests that share a synthesis kernel (a tile list over up to kSynthBatchMax
-// requests), or a request's own launches (ENERGY, staged synthesis).  Table builds, copies
-// and launches run on the scheduler's worker thread with the scheduler lock released.
+// requests), or a request's own launches (ENERGY, the W/U synthesis of L_h > 16).  Table
+// builds, copies and launches run on the scheduler's worker thread with the scheduler lock
+// released.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -86,7 +87,7 @@ public:
     const void* group_key(const slsht::SchedRequest& r) override {
         const slsht::DevPlan& P = static_cast<ExecState*>(r.exec)->P;
         if (P.d.output_mode != SLSHT_OUT_FULL) return nullptr;    // ENERGY runs alone
-        return slsht::synthesis_kernel_key(P);                     // unique for staged plans
+        return slsht::synthesis_kernel_key(P);                     // unique for W/U plans
     }
 
     struct DevPtrs {
@@ -94,7 +95,7 @@ public:
         void* g;
         void* work;
     };
-    // Input block layout: [f][h][A][ENERGY or staged-synthesis workspace], 256-B aligned.
+    // Input block layout: [f][h][A][ENERGY or W/U-synthesis workspace], 256-B aligned.
     DevPtrs ptrs(const slsht::SchedRequest& r) const {
         char* in = base + r.in_off;
         DevPtrs p;

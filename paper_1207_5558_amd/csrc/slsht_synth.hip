@@ -323,8 +323,9 @@ static const void* synth_fn(const DevPlan& P, bool batch = false) {
     }
 }
 
-// Staged plans run their own launches (W table, U GEMM, phi stage per chunk), so each one
-// gets a key of its own and is never grouped with other transforms.
+// Plans on the W/U path (L_h > 16, slsht_staged.hip) run their own launches (W table, A
+// fragments, the W/U kernel), so each one gets a key of its own and is never grouped with
+// other transforms.
 const void* synthesis_kernel_key(const DevPlan& P) { return P.staged ? (const void*)&P : synth_fn(P); }
 
 // Theta rows per block: stages 1-2 run between barriers with no stores in flight, so
@@ -400,7 +401,7 @@ hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const*
                                   const double2* const* h, void* const* g, int n, hipStream_t s) {
     if (n < 1 || n > kSynthBatchMax) return hipErrorInvalidValue;
     if (P[0]->staged) {
-        // staged plans are grouped alone (their key is unique)
+        // W/U plans are grouped alone (their key is unique)
         if (n != 1) return hipErrorInvalidValue;
         return launch_synthesis_staged(*P[0], A[0], h[0], g[0], s);
     }
