@@ -211,23 +211,23 @@ def test_largest_phi_grid_sampled(L_h, prec, tol):
     dict(L_f=6, L_h=18, l_lo=2, l_hi=8, n_phi=35, n_omega=5, n_az=3),           # steerable
     dict(L_f=5, L_h=17, l_lo=0, l_hi=6, n_phi=33, n_omega=33, real_pair=True),  # L_h = 17
 ])
-def test_staged_synthesis_whole_grid(case, prec, tol):
-    """Band-limits above 16 take the staged FULL path (W table, U GEMM over the items, phi
-    stage from the stored P/M rows): whole grid against the oracle, with a steerable window
-    and with the real-pair path."""
-    announce(f"staged whole grid {case} {prec}")
+def test_wu_synthesis_whole_grid(case, prec, tol):
+    """Band-limits above 16 take the W/U path (W table, U GEMM over the items and phi stage
+    in one kernel, the P|M rows in LDS): whole grid against the oracle, with a steerable
+    window and with the real-pair path."""
+    announce(f"W/U whole grid {case} {prec}")
     f, h, g, ref = _full_case(**case, prec=prec, seed=41)
     errs = per_l_rel_err(g, ref, case["l_lo"], case["l_hi"])
     assert max(errs.values()) <= tol, errs
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
-def test_staged_synthesis_several_chunks_sampled(prec, tol):
-    """L_f = 64, L_h = 32, l in [80, 95) (2625 items, 191 x 96 x 63 grid): the P/M rows of
-    all items exceed the staged path's 4 GiB chunk, so the U GEMM and the phi stage run in
-    2 (FP32) or 4 (FP64) chunks of items; seeded rotations against the oracle, including
-    the first and last item of every chunk's neighbourhood."""
-    announce(f"staged chunks {prec}")
+def test_wu_synthesis_theta_runs_sampled(prec, tol):
+    """L_f = 64, L_h = 32, l in [80, 95) (2625 items, 191 x 96 x 63 grid) on the W/U path:
+    enough item tiles that each W/U block loops over a run of theta rows (15 FP32, 31 FP64)
+    and the tiles spread over every XCD's run; seeded rotations against the oracle,
+    including the first and the last grid point."""
+    announce(f"W/U theta runs {prec}")
     rng = np.random.default_rng(43)
     L_f, L_h, l_lo, l_hi, n_phi, n_omega = 64, 32, 80, 95, 191, 63
     n_theta = (n_phi + 1) // 2
@@ -241,6 +241,29 @@ def test_staged_synthesis_several_chunks_sampled(prec, tol):
     idx[1] = (n_phi - 1, n_theta - 1, n_omega - 1)
     ref = oracle_g_grid(f, h, L_f, L_h, l_lo, l_hi, n_phi, n_theta, n_omega, idx)
     errs = per_l_rel_err(gather_rho(g, idx), ref, l_lo, l_hi, axis=1)
+    del g
+    torch.cuda.empty_cache()
+    assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_minimal_grid_all_degrees_sampled(prec, tol):
+    """The paper's timing setting (Section V) at L_f = 66: L_h = 18, every l < L_f + 17
+    (6889 items), the minimal grid 35 x 18 x 35; the W/U blocks take runs of theta rows.
+    Seeded rotations against the oracle."""
+    announce(f"minimal grid L_f=66 {prec}")
+    rng = np.random.default_rng(47)
+    L_f, L_h = 66, 18
+    K = 2 * L_h - 1
+    f = draw_coefficients(rng, L_f, 2.0, True)
+    h = draw_window(rng, L_h)
+    plan = api.Plan(api.make_desc(L_f, L_h, 0, L_f + L_h - 1, K, L_h, K, precision=prec))
+    g = plan.forward(dev(f), dev(h))
+    idx = np.stack([rng.integers(0, K, 24), rng.integers(0, L_h, 24), rng.integers(0, K, 24)], 1)
+    idx[0] = (0, 0, 0)
+    idx[1] = (K - 1, L_h - 1, K - 1)
+    ref = oracle_g_grid(f, h, L_f, L_h, 0, L_f + L_h - 1, K, L_h, K, idx)
+    errs = per_l_rel_err(gather_rho(g, idx), ref, 0, L_f + L_h - 1, axis=1)
     del g
     torch.cuda.empty_cache()
     assert max(errs.values()) <= tol, errs
