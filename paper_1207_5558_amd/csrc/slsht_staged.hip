@@ -176,7 +176,28 @@ __global__ void __launch_bounds__(64) staged_afrag_kernel(const double2* __restr
 struct WUArgs {
     int L, n_omega, ncw, n_theta_out, n_phi, nslot, l_lo, real_pair, n_items;
     int afrag_tile, n_itiles, n_ctiles, tchunk, n_tchunks;
+    uint32_t kmask[8];           // k of U_{+-k} taken by each wave (bit k)
 };
+
+// Splits the k of U_{+-k} over `nw` waves: costliest first (MFMA steps in groups of 4,
+// four GEMMs, two for k = 0), each to the wave with the least work so far.
+static void wu_kmasks(int L, int nw, uint32_t* mask) {
+    auto cost = [&](int k) { return ((u_steps(L, k) + 3) / 4) * (k ? 4 : 2); };
+    int load[8] = {0};
+    bool used[SLSHT_MAX_LH] = {false};
+    for (int w = 0; w < 8; ++w) mask[w] = 0;
+    for (int n = 0; n < L; ++n) {
+        int k = -1;
+        for (int c = 0; c < L; ++c)
+            if (!used[c] && (k < 0 || cost(c) > cost(k))) k = c;
+        used[k] = true;
+        int best = 0;
+        for (int w = 1; w < nw; ++w)
+            if (load[w] < load[best]) best = w;
+        load[best] += cost(k);
+        mask[best] |= 1u << k;
+    }
+}
 
 // offset (in 64-lane fragment steps) of U_{+k}'s A fragments within a 16-item tile
 __device__ __forceinline__ int afrag_off(int L, int k) {
@@ -234,9 +255,12 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
     const T* aft = af + (int64_t)(item0 / 16) * a.afrag_tile + j4 * 16 + (item0 % 16) + i16;
     __syncthreads();
 
+    const uint32_t kmask = a.kmask[wave];                  // this wave's k of U_{+-k}
+
     for (int t = t_begin; t < t_end; ++t) {
         const V* Wt = W + (int64_t)t * L * L * ncw + c0 + i16;
-        for (int k = wave; k < L; k += nw) {
+        for (uint32_t km = kmask; km; km &= km - 1) {
+            const int k = __builtin_ctz(km);
             const int steps = u_steps(L, k);
             const int off = afrag_off(L, k);
             const int lastp = L - k - 1;
@@ -321,6 +345,7 @@ static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* 
     a.n_ctiles = sg.n_ctiles;
     a.tchunk = sg.tchunk;
     a.n_tchunks = sg.n_tchunks;
+    wu_kmasks(sg.L, sg.threads / 64, a.kmask);
     const int64_t nblk = (int64_t)sg.n_itiles * sg.n_ctiles * sg.n_tchunks;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
     const void* fn = (const void*)wu_phi_kernel<T, LH, IT>;
