@@ -393,8 +393,9 @@ hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, f
     float* af = reinterpret_cast<float*>(ws + g.off_af);
     float* pm = reinterpret_cast<float*>(ws + g.off_pm);
     float* ep = reinterpret_cast<float*>(ws + g.off_ep);
-    hipError_t e = launch_wtable(P.T->dtab, true, h, W, false, g.L, g.N, g.n_omega, g.ncw,
-                                 g.n_theta_out, s);
+    const WtableLayout lay{0, (int64_t)g.L * g.L * g.ncw, g.ncw, g.ncw, 0};
+    hipError_t e = launch_wtable(P.T->dtab, true, h, W, false, g.L, g.N, g.n_omega,
+                                 g.n_theta_out, lay, s);
     if (e != hipSuccess) return e;
 
     const int ti = g.tpw == 4 ? 0 : (g.tpw == 8 ? 1 : (g.tpw == 12 ? 2 : 3));

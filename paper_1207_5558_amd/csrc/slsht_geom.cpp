@@ -112,8 +112,9 @@ bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& 
     g.L = d.L_h;
     g.N = n_az_of(d);
     g.n_omega = d.n_omega;
-    g.ncw = (d.n_omega + 15) / 16 * 16;
     g.n_theta_out = n_theta_out;
+    g.n_cols = n_theta_out * d.n_omega;
+    g.ncol = (g.n_cols + 15) / 16 * 16;
     g.l_lo = d.l_lo;
     g.real_pair = (d.flags & SLSHT_REAL_PAIR) ? 1 : 0;
     g.f64 = d.precision == SLSHT_FP64 ? 1 : 0;
@@ -123,22 +124,23 @@ bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& 
     for (int k = 0; k < g.L; ++k) steps += (k ? 2 : 1) * u_steps(g.L, k);
     g.afrag_tile = steps * 64;
     const size_t vb = g.f64 ? 16 : 8, rb = g.f64 ? 8 : 4;
-    // block: `it` items x 16 omega columns; its P|M rows (2L + 1 complex each) sit in LDS
+    // block: `it` items x 16 (omega, theta row) columns at a time; its P|M rows (2L + 1
+    // complex each) sit in LDS.  The columns run over omega and theta rows together, so only
+    // the last of the n_omega * n_theta_out columns' tiles carries padding.
     g.it = (size_t)16 * 16 * (2 * g.L + 1) * vb <= kWuMaxLds ? 16 : 8;
     g.lds = (size_t)g.it * 16 * (2 * g.L + 1) * vb;
     g.threads = g.lds > 80 * 1024 ? 512 : 256;
     g.n_itiles = ((n_items + g.it - 1) / g.it + 7) / 8 * 8;
-    g.n_ctiles = g.ncw / 16;
-    // theta rows per block: as many as keep >= 4096 blocks in the grid
-    const int64_t units = (int64_t)g.n_itiles * g.n_ctiles;
-    int tc = (int)std::max<int64_t>(1, units * n_theta_out / 4096);
-    tc = std::min(tc, std::max(1, n_theta_out));
-    g.n_tchunks = (n_theta_out + tc - 1) / tc;
-    g.tchunk = (n_theta_out + g.n_tchunks - 1) / g.n_tchunks;
+    g.n_ctiles = g.ncol / 16;
+    // column tiles per block: as many as keep >= 4096 blocks in the grid
+    int cc = (int)std::max<int64_t>(1, (int64_t)g.n_itiles * g.n_ctiles / 4096);
+    cc = std::min(cc, std::max(1, g.n_ctiles));
+    g.n_cchunks = (g.n_ctiles + cc - 1) / cc;
+    g.cchunk = (g.n_ctiles + g.n_cchunks - 1) / g.n_cchunks;
     auto al = [](size_t n) { return (n + 255) / 256 * 256; };
     size_t off = 0;
     g.off_w = off;
-    off += al((size_t)n_theta_out * g.L * g.L * g.ncw * vb);
+    off += al((size_t)g.L * g.L * g.ncol * vb);
     g.off_af = off;
     off += al((size_t)g.ntiles * g.afrag_tile * rb);
     g.total = off;

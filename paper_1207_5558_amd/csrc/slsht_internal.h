@@ -60,13 +60,14 @@ struct EnergyGeom {
 // Geometry of the staged FULL synthesis (slsht_staged.hip; window band-limits above 16,
 // n_omega <= 64): U GEMM over chunks of items, then the phi stage from the P/M rows.
 struct StagedGeom {
-    int L, N, n_omega, ncw;          // band-limit, n_az, omega (padded to 16s)
+    int L, N, n_omega;               // band-limit, n_az, omega samples
     int n_theta_out, l_lo, real_pair, f64;
+    int n_cols, ncol;                // (omega, theta row) columns n_omega * n_theta_out; to 16s
     int n_items, ntiles;             // items, 16-item tiles of the A fragments
     int afrag_tile;                  // elements of A fragments per 16-item tile
     int it;                          // items per block of the W/U kernel (16 or 8)
-    int n_itiles, n_ctiles;          // item tiles (rounded up to 8s), 16-column omega tiles
-    int tchunk, n_tchunks;           // theta rows per block, theta chunks
+    int n_itiles, n_ctiles;          // item tiles (rounded up to 8s), 16-column tiles
+    int cchunk, n_cchunks;           // column tiles per block, column chunks
     int threads;                     // threads per block
     size_t lds;                      // LDS bytes per block
     size_t off_w, off_af, total;     // workspace byte offsets and size
@@ -163,11 +164,23 @@ hipError_t launch_synthesis_batch(const DevPlan* const* P, const double2* const*
 // ENERGY path: W table, A fragments, P/M slabs and partial energies in P.ework.
 hipError_t launch_energy(const DevPlan& P, const double2* A, const double2* h, float* E,
                          hipStream_t s);
+// Where the W table puts entry (theta row t, row r = wq_off(q) + p - |q|, omega column c):
+//   tiled = 0: W[t * tstride + r * rstride + c]; each theta row writes columns c < cw, those
+//              with c >= n_omega as zeros;
+//   tiled = 1: by tiles of 16 of the columns col = c * n_theta_out + t (theta fastest), each
+//              tile holding all L_h^2 rows: W[((col / 16) * L_h^2 + r) * 16 + col % 16]; the
+//              columns from n_omega * n_theta_out up to ncol (a multiple of 16) are zeros.
+struct WtableLayout {
+    int tiled;
+    int64_t tstride, rstride;
+    int cw, ncol;
+};
 // W^p_q(theta_b, omega_c) = sum_{q'} h_p^{q'} d^p_{q,q'}(theta_b) e^{-i q' omega_c} for every
 // theta row of the table (slsht_staged.hip): d in FP64 (d64) or FP32, W stored complex128
-// (w64) or complex64 as [theta][wq_off(q) + p - |q|][ncw].
+// (w64) or complex64 in layout `lay`.
 hipError_t launch_wtable(const void* dtab, bool d64, const double2* h, void* W, bool w64, int L,
-                         int N, int n_omega, int ncw, int n_theta_out, hipStream_t s);
+                         int N, int n_omega, int n_theta_out, const WtableLayout& lay,
+                         hipStream_t s);
 // FULL synthesis through the W table and the U GEMM (W/U kernel): geometry (false if the
 // plan does not qualify) and launch.
 bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& g);

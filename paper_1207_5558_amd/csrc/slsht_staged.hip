@@ -11,8 +11,9 @@
 // v_mfma_f32_16x16x4f32 for FP32-mixed).  Kernels:
 //   wtable_kernel       W of every theta row (FP64 sums; stored in the plan precision)
 //   staged_afrag_kernel A^p_{+-k} of the items in MFMA A-fragment order
-//   wu_phi_kernel       per block of items, omega columns and theta rows: U, the fold into
-//                       P_k, M_k in LDS, then the phi stage and store (slsht_phi.h)
+//   wu_phi_kernel       per block of items and a run of (theta row, omega) column tiles:
+//                       U, the fold into P_k, M_k in LDS, then the phi stage and store
+//                       (slsht_phi.h)
 // MFMA lane layouts (gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16]; the FP32 form
 // returns D rows 4(l/16)+r, the FP64 form rows (l/16)+4r, of column l%16.
 #include "slsht_device.h"
@@ -52,13 +53,13 @@ __host__ __device__ inline int u_steps(int L, int k) { return (L - k + 1) / 2; }
 // W^p_q(theta_b, omega_c), one block per (theta row, q), q ordered 0, +1, -1, +2, -2, ...
 // (row offset wq_off).  h_p^{q'} d^p_{q,q'}(theta_b) is staged in LDS (canonical table entries
 // through the symmetries of Section IV-B); each thread sums one (p, c) over q' against
-// cos/sin(2 pi j / n_omega) at j = q' c mod n_omega, in FP64.  Columns c >= n_omega (padding
-// to ncw) are written as zeros.
+// cos/sin(2 pi j / n_omega) at j = q' c mod n_omega, in FP64.  Where entry (theta row t,
+// row r, column c) sits, and which padding columns are written as zeros: WtableLayout.
 template <typename DT, typename OV>
 __global__ void __launch_bounds__(256) wtable_kernel(const double2* __restrict__ h,
                                                      const DT* __restrict__ dtab,
                                                      OV* __restrict__ W, int L, int N,
-                                                     int n_omega, int ncw) {
+                                                     int n_omega, const WtableLayout lay) {
     __shared__ double2 hd[SLSHT_MAX_LH * (2 * SLSHT_MAX_LH - 1)];
     extern __shared__ double2 tw[];                      // [n_omega] (dynamic)
     const int K = 2 * L - 1;
@@ -87,9 +88,10 @@ __global__ void __launch_bounds__(256) wtable_kernel(const double2* __restrict__
         tw[j] = vmk<double2>(c, s);
     }
     __syncthreads();
-    OV* out = W + ((int64_t)t * L * L + wq_off(L, q)) * ncw;
-    for (int i = threadIdx.x; i < (L - k) * ncw; i += blockDim.x) {
-        const int pr = i / ncw, c = i - pr * ncw, p = k + pr;
+    const int r0 = wq_off(L, q), n_theta = gridDim.x;
+    const int cw = lay.tiled ? n_omega : lay.cw;
+    for (int i = threadIdx.x; i < (L - k) * cw; i += blockDim.x) {
+        const int pr = i / cw, c = i - pr * cw, p = k + pr;
         double sr = 0.0, si = 0.0;
         if (c < n_omega) {
             const int P = min(p, N - 1);
@@ -104,24 +106,41 @@ __global__ void __launch_bounds__(256) wtable_kernel(const double2* __restrict__
                 if (idx >= n_omega) idx -= n_omega;
             }
         }
-        out[i] = vmk<OV>((decltype(OV::x))sr, (decltype(OV::x))si);
+        int64_t at;
+        if (lay.tiled) {
+            const int64_t col = (int64_t)c * n_theta + t;
+            at = ((col >> 4) * L * L + r0 + pr) * 16 + (col & 15);
+        } else {
+            at = (int64_t)t * lay.tstride + (int64_t)(r0 + pr) * lay.rstride + c;
+        }
+        W[at] = vmk<OV>((decltype(OV::x))sr, (decltype(OV::x))si);
+    }
+    if (lay.tiled && t == 0) {                           // the last tile's padding columns
+        const int64_t c0 = (int64_t)n_omega * n_theta;
+        const int pad = (int)(lay.ncol - c0);
+        for (int i = threadIdx.x; i < (L - k) * pad; i += blockDim.x) {
+            const int pr = i / pad;
+            const int64_t col = c0 + (i - pr * pad);
+            W[((col >> 4) * L * L + r0 + pr) * 16 + (col & 15)] = vmk<OV>(0, 0);
+        }
     }
 }
 
 hipError_t launch_wtable(const void* dtab, bool d64, const double2* h, void* W, bool w64, int L,
-                         int N, int n_omega, int ncw, int n_theta_out, hipStream_t s) {
-    if (n_omega < 1 || n_omega > kWtableMaxOmega) return hipErrorInvalidValue;
+                         int N, int n_omega, int n_theta_out, const WtableLayout& lay,
+                         hipStream_t s) {
+    if (n_omega < 1 || n_omega > kWtableMaxOmega || n_theta_out < 1) return hipErrorInvalidValue;
     const dim3 grid(n_theta_out, 2 * L - 1), block(256);
     const size_t lds = (size_t)n_omega * sizeof(double2);
     if (d64 && w64)
         hipLaunchKernelGGL((wtable_kernel<double, double2>), grid, block, lds, s, h,
-                           (const double*)dtab, (double2*)W, L, N, n_omega, ncw);
+                           (const double*)dtab, (double2*)W, L, N, n_omega, lay);
     else if (d64)
         hipLaunchKernelGGL((wtable_kernel<double, float2>), grid, block, lds, s, h,
-                           (const double*)dtab, (float2*)W, L, N, n_omega, ncw);
+                           (const double*)dtab, (float2*)W, L, N, n_omega, lay);
     else
         hipLaunchKernelGGL((wtable_kernel<float, float2>), grid, block, lds, s, h,
-                           (const float*)dtab, (float2*)W, L, N, n_omega, ncw);
+                           (const float*)dtab, (float2*)W, L, N, n_omega, lay);
     return hipGetLastError();
 }
 
@@ -160,9 +179,11 @@ __global__ void __launch_bounds__(64) staged_afrag_kernel(const double2* __restr
 }
 
 // ------------------------------------------------------------------------------
-// The W/U kernel: one block = `IT` items x 16 omega columns x a run of theta rows.  Per
-// theta row:
-//   1. U_{+-k}(theta, omega_c) for the block's items and columns, as complex GEMMs on real
+// The W/U kernel: one block = `IT` items x a run of tiles of 16 columns, a column being an
+// (omega, theta row) pair: col = c n_theta_out + t over all n_omega * n_theta_out of them, the
+// order of the output rows (A depends on neither, so a tile may span omega values, and only
+// the last tile is padded).  Per column tile:
+//   1. U_{+-k}(theta_t, omega_c) for the block's items and columns, as complex GEMMs on real
 //      MFMAs (the complex inner index p expanded to (Re, Im), B = [[W_re, W_im],
 //      [-W_im, W_re]] row pairs); the waves split the k, and each folds its U_{+-k} into
 //      P_k = U_k + U_{-k}, M_k = -i (U_k - U_{-k}) and writes them to the block's P|M rows
@@ -174,8 +195,8 @@ __global__ void __launch_bounds__(64) staged_afrag_kernel(const double2* __restr
 // Blocks are laid out so that those sharing an item tile (the same A fragments) run on one
 // XCD: block b goes to XCD b mod 8 under round-robin dispatch.
 struct WUArgs {
-    int L, n_omega, ncw, n_theta_out, n_phi, nslot, l_lo, real_pair, n_items;
-    int afrag_tile, n_itiles, n_ctiles, tchunk, n_tchunks;
+    int L, n_omega, n_cols, ncol, n_theta_out, n_phi, nslot, l_lo, real_pair, n_items;
+    int afrag_tile, n_itiles, n_ctiles, cchunk, n_cchunks;
     uint32_t kmask[8];           // k of U_{+-k} taken by each wave (bit k)
 };
 
@@ -218,21 +239,18 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* PM_s = reinterpret_cast<V*>(smem_raw);        // [IT * 16 rows][2L + 1]
     __shared__ int64_t s_lm[IT], s_mir[IT];
+    __shared__ int64_t s_roff[16];                   // output row offset of each column of the tile
     __shared__ T s_sign[IT];
 
     const int b = blockIdx.x;
     const int xcd = b & 7, j = b >> 3;
-    const int n_inner = a.n_ctiles * a.n_tchunks;
-    const int grp = j / n_inner;
+    const int grp = j / a.n_cchunks;
     const int itile = xcd * (a.n_itiles >> 3) + grp;
-    const int inner = j - grp * n_inner;
-    const int ctile = inner % a.n_ctiles;
-    const int tch = inner / a.n_ctiles;
+    const int cch = j - grp * a.n_cchunks;
     const int item0 = itile * IT;
     if (item0 >= a.n_items) return;                  // whole block: uniform
-    const int L = a.L, pms = 2 * L + 1, ncw = a.ncw;
-    const int c0 = ctile * 16;
-    const int t_begin = tch * a.tchunk, t_end = min(a.n_theta_out, t_begin + a.tchunk);
+    const int L = a.L, pms = 2 * L + 1;
+    const int ct_begin = cch * a.cchunk, ct_end = min(a.n_ctiles, ct_begin + a.cchunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int i16 = lane & 15, j4 = lane >> 4;
 
@@ -257,15 +275,21 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
 
     const uint32_t kmask = a.kmask[wave];                  // this wave's k of U_{+-k}
 
-    for (int t = t_begin; t < t_end; ++t) {
-        const V* Wt = W + (int64_t)t * L * L * ncw + c0 + i16;
+    // column tiles: 16 consecutive columns col = c * n_theta_out + t, which is also the
+    // output row (omega_c, theta_t) of every item
+    for (int ct = ct_begin; ct < ct_end; ++ct) {
+        if (tid < 16) {
+            const int col = ct * 16 + tid;
+            s_roff[tid] = col < a.n_cols ? (int64_t)col * a.n_phi : -1;
+        }
+        const V* Wt = W + (int64_t)ct * L * L * 16 + i16;     // the tile's rows, 16 columns each
         for (uint32_t km = kmask; km; km &= km - 1) {
             const int k = __builtin_ctz(km);
             const int steps = u_steps(L, k);
             const int off = afrag_off(L, k);
             const int lastp = L - k - 1;
-            const V* wpk = Wt + (int64_t)wq_off(L, k) * ncw;
-            const V* wmk = wpk + (int64_t)(L - k) * ncw;
+            const V* wpk = Wt + wq_off(L, k) * 16;
+            const V* wmk = wpk + (L - k) * 16;
             Acc upr = {0, 0, 0, 0}, upi = {0, 0, 0, 0}, umr = {0, 0, 0, 0}, umi = {0, 0, 0, 0};
             // the p-sum in groups of SB MFMA steps: loads of a group first, then its MFMAs
             for (int s0 = 0; s0 < steps; s0 += SB) {
@@ -279,8 +303,8 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
                     const bool in = s < steps;
                     ap[u] = (in && arow) ? aft[(int64_t)(off + s) * 64] : T(0);
                     am[u] = (in && arow && k) ? aft[(int64_t)(off + steps + s) * 64] : T(0);
-                    wp[u] = in ? wpk[(int64_t)rp * ncw] : vmk<V>(0, 0);
-                    wm[u] = (in && k) ? wmk[(int64_t)rp * ncw] : vmk<V>(0, 0);
+                    wp[u] = in ? wpk[rp * 16] : vmk<V>(0, 0);
+                    wm[u] = (in && k) ? wmk[rp * 16] : vmk<V>(0, 0);
                 }
 #pragma unroll
                 for (int u = 0; u < SB; ++u) {
@@ -302,18 +326,17 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
             }
         }
         __syncthreads();
-        const int n_theta = a.n_theta_out, n_phi = a.n_phi, n_omega = a.n_omega;
-        phi_stage_mfma<T, LH>(PM_s, pms, L, IT * 16, L, twphi, a.nslot, n_phi,
+        phi_stage_mfma<T, LH>(PM_s, pms, L, IT * 16, L, twphi, a.nslot, a.n_phi,
                               [&](int rr, V*& out, V*& mout, T& ms) {
-                                  const int item = rr >> 4, c = c0 + (rr & 15);
+                                  const int item = rr >> 4;
                                   const int64_t base = s_lm[item];
-                                  if (base < 0 || c >= n_omega) {
+                                  const int64_t rowoff = s_roff[rr & 15];
+                                  if (base < 0 || rowoff < 0) {
                                       out = nullptr;
                                       mout = nullptr;
                                       ms = T(1);
                                       return;
                                   }
-                                  const int64_t rowoff = ((int64_t)c * n_theta + t) * n_phi;
                                   out = g + base + rowoff;
                                   const int64_t mb = s_mir[item];
                                   mout = mb >= 0 ? g + mb + rowoff : nullptr;
@@ -333,7 +356,8 @@ static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* 
     WUArgs a;
     a.L = sg.L;
     a.n_omega = sg.n_omega;
-    a.ncw = sg.ncw;
+    a.n_cols = sg.n_cols;
+    a.ncol = sg.ncol;
     a.n_theta_out = sg.n_theta_out;
     a.n_phi = P.d.n_phi;
     a.nslot = P.nslot_phi;
@@ -343,10 +367,10 @@ static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* 
     a.afrag_tile = sg.afrag_tile;
     a.n_itiles = sg.n_itiles;
     a.n_ctiles = sg.n_ctiles;
-    a.tchunk = sg.tchunk;
-    a.n_tchunks = sg.n_tchunks;
+    a.cchunk = sg.cchunk;
+    a.n_cchunks = sg.n_cchunks;
     wu_kmasks(sg.L, sg.threads / 64, a.kmask);
-    const int64_t nblk = (int64_t)sg.n_itiles * sg.n_ctiles * sg.n_tchunks;
+    const int64_t nblk = (int64_t)sg.n_itiles * sg.n_cchunks;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
     const void* fn = (const void*)wu_phi_kernel<T, LH, IT>;
     if (sg.lds > 64 * 1024)
@@ -366,8 +390,10 @@ hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const dou
     if (!ws) return hipErrorInvalidValue;
     void* W = ws + sg.off_w;
     void* af = ws + sg.off_af;
+    // W by tiles of 16 (omega, theta row) columns
+    const WtableLayout lay{1, 0, 0, 0, sg.ncol};
     hipError_t e = launch_wtable(P.T->dtab, sg.f64 != 0, h, W, sg.f64 != 0, sg.L, sg.N,
-                                 sg.n_omega, sg.ncw, sg.n_theta_out, s);
+                                 sg.n_omega, sg.n_theta_out, lay, s);
     if (e != hipSuccess) return e;
     if (sg.f64)
         hipLaunchKernelGGL(staged_afrag_kernel<double>, dim3(sg.ntiles), dim3(64), 0, s, A,
