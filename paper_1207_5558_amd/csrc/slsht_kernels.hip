@@ -115,6 +115,26 @@ hipError_t launch_wigner_table(const DevPlan& P, hipStream_t s) {
 // matched, normalised by sum (2j+1) F^2 = 1 and signed so that F(jmax) has the
 // sign (-1)^(j2-j3-m1).  Nothing is stored per j: the caller's sink consumes
 // the unnormalised values and the returned factors finish the job.
+// Inside the two loops each step needs A(j) and a division by j A(j): A and 1/A come from
+// one reciprocal square root refined by Goldschmidt's iteration, 1/j from a table `invj`
+// (invj[j - jbase] = 1/j), so no step runs a full-precision square root or division.
+
+// sqrt(t) and 1/sqrt(t) for t >= 1 (0 and 0 for t <= 0): v_rsq_f64's estimate y, then two
+// steps of Goldschmidt's coupled iteration g -> sqrt(t), h -> 1/(2 sqrt(t)) (each squares
+// the relative error), and a last Newton correction of g.
+__device__ __forceinline__ void sqrt_and_rsqrt(double t, double& sq, double& rs) {
+    const double y = __builtin_amdgcn_rsq(t > 0.0 ? t : 1.0);
+    double g = t * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, t);
+    sq = t > 0.0 ? fma(d, h, g) : 0.0;
+    rs = t > 0.0 ? 2.0 * h : 0.0;
+}
 
 struct ThreeJ {
     int jmin, jmax, jm;
@@ -123,13 +143,15 @@ struct ThreeJ {
 };
 
 template <class Sink>
-__device__ ThreeJ threej_two_sided(int j2, int j3, int m2, int m3, Sink& sink) {
+__device__ ThreeJ threej_two_sided(int j2, int j3, int m2, int m3, const double* invj, int jbase,
+                                   Sink& sink) {
     const int m1 = -m2 - m3;
     const double dj2 = j2, dj3 = j3, dm1 = m1, dm2 = m2, dm3 = m3;
     const double dd = dj2 - dj3, ss = (dj2 + dj3 + 1) * (dj2 + dj3 + 1);
     const double bc = (dj2 * (dj2 + 1) - dj3 * (dj3 + 1)) * dm1, dm = dm3 - dm2;
+    auto At = [&](double j) { return (j * j - dd * dd) * (ss - j * j) * (j * j - dm1 * dm1); };
     auto Af = [&](double j) {
-        const double t = (j * j - dd * dd) * (ss - j * j) * (j * j - dm1 * dm1);
+        const double t = At(j);
         return t > 0.0 ? sqrt(t) : 0.0;
     };
     auto Bf = [&](double j) { return -(2 * j + 1) * (bc - j * (j + 1) * dm); };
@@ -156,8 +178,9 @@ __device__ ThreeJ threej_two_sided(int j2, int j3, int m2, int m3, Sink& sink) {
             double Aj = Af((double)jm);
             while (jm < r.jmax) {
                 const double j = jm;
-                const double Aj1 = Af(j + 1);
-                const double Fn = -(Bf(j) * Fcur + (j + 1) * Aj * Fprev) / (j * Aj1);
+                double Aj1, rAj1;
+                sqrt_and_rsqrt(At(j + 1), Aj1, rAj1);
+                const double Fn = -(Bf(j) * Fcur + (j + 1) * Aj * Fprev) * (invj[jm - jbase] * rAj1);
                 if (fabs(Fn) <= fabs(Fcur)) break;
                 ++jm;
                 Fprev = Fcur;
@@ -178,14 +201,15 @@ __device__ ThreeJ threej_two_sided(int j2, int j3, int m2, int m3, Sink& sink) {
         int j = r.jmax;
         double Bc = 1.0, Bn = 0.0, topb = 1.0, norm_b = (2.0 * j + 1.0);
         sink.bwd(j, 1.0);
-        double Aj = Af((double)j), Aj1 = 0.0;
+        double Aj, rAj, Aj1 = 0.0;
+        sqrt_and_rsqrt(At((double)j), Aj, rAj);
         for (;;) {
             const double dj = j;
-            const double Bp = -(Bf(dj) * Bc + dj * Aj1 * Bn) / ((dj + 1) * Aj);
+            const double Bp = -(Bf(dj) * Bc + dj * Aj1 * Bn) * (invj[j + 1 - jbase] * rAj);
             --j;
             Bn = Bc; Bc = Bp; Aj1 = Aj;
             if (j == jm) break;
-            Aj = Af((double)j);
+            sqrt_and_rsqrt(At((double)j), Aj, rAj);
             norm_b += (2.0 * j + 1.0) * Bc * Bc;
             sink.bwd(j, Bc);
             if (fabs(Bc) > 1e120) {
@@ -216,15 +240,16 @@ struct RowSink {
     __device__ void rescale_bwd(double s) { for (int j = jb_lo; j <= jmax; ++j) row[j - jmin] *= s; }
 };
 
-// Accumulates sum_j w_j F(j) with w_j = sqrt(2j+1) Z(j) f_j^{mp} for j < L_f.
+// Accumulates sum_j w_j F(j) with w_j = sqrt(2j+1) Z(j) f_j^{mp} for j < L_f.  Z(j) vanishes
+// where j + p + l is odd (the parity rule of (j p l; 0 0 0)); those terms are skipped.
 struct DotSink {
     const double2* f;
-    const double* z;     // Z row for this p: (j p l; 0 0 0) at index j - zlo
-    int zlo, L_f, mp;
+    const double* z;     // Z row for this p: sqrt(2j+1) (j p l; 0 0 0) at index j - zlo
+    int zlo, L_f, mp, par;
     double fr, fi, br, bi;
     __device__ void add(int j, double v, double& ar, double& ai) {
-        if (j >= L_f) return;
-        const double w = sqrt(2.0 * j + 1.0) * z[j - zlo] * v;
+        if (j >= L_f || ((j ^ par) & 1)) return;
+        const double w = z[j - zlo] * v;
         const double2 c = f[(int64_t)j * j + j + mp];
         ar += w * c.x;
         ai += w * c.y;
@@ -238,10 +263,15 @@ struct DotSink {
 __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restrict__ A, int L_f,
                                 int L_h, int l_lo) {
     __shared__ double Z[SLSHT_MAX_LH * SLSHT_MAX_LH];
+    __shared__ double invj[2 * SLSHT_MAX_LH + 1];
     const int lm = blockIdx.x;
     int l, m;
     lm_of(lm + l_lo * l_lo, l, m);
-    // Z rows: (j p l; 0 0 0) for j in [|l-p|, l+p], row p at offset p*p.
+    // every recursion below runs over j in [|l - p|, l + p], p < L_h
+    const int jbase = l - L_h + 1 > 1 ? l - L_h + 1 : 1;
+    for (int i = threadIdx.x; i < 2 * L_h + 1; i += blockDim.x) invj[i] = 1.0 / (double)(jbase + i);
+    __syncthreads();
+    // Z rows: sqrt(2j+1) (j p l; 0 0 0) for j in [|l-p|, l+p], row p at offset p*p.
     for (int p = threadIdx.x; p < L_h; p += blockDim.x) {
         RowSink rs;
         rs.row = Z + p * p;
@@ -249,9 +279,9 @@ __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restri
         rs.jmax = l + p;
         rs.jm_hi = rs.jmin;
         rs.jb_lo = rs.jmax;
-        const ThreeJ t = threej_two_sided(p, l, 0, 0, rs);
+        const ThreeJ t = threej_two_sided(p, l, 0, 0, invj, jbase, rs);
         for (int j = t.jmin; j <= t.jmax; ++j)
-            rs.row[j - t.jmin] *= (j <= t.jm ? t.scale : t.c * t.scale);
+            rs.row[j - t.jmin] *= (j <= t.jm ? t.scale : t.c * t.scale) * sqrt(2.0 * j + 1.0);
     }
     __syncthreads();
     const double sm = (m & 1) ? -1.0 : 1.0;
@@ -265,8 +295,9 @@ __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restri
         ds.zlo = l > p ? l - p : p - l;
         ds.L_f = L_f;
         ds.mp = m - q;
+        ds.par = (p + l) & 1;
         ds.fr = ds.fi = ds.br = ds.bi = 0.0;
-        const ThreeJ t = threej_two_sided(p, l, q, -m, ds);
+        const ThreeJ t = threej_two_sided(p, l, q, -m, invj, jbase, ds);
         const double k = pref * sqrt(2.0 * p + 1.0) * t.scale;
         double2 out;
         out.x = k * (ds.fr + t.c * ds.br);
@@ -278,7 +309,9 @@ __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restri
 hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipStream_t s) {
     const int n_lm = P.d.l_hi * P.d.l_hi - P.d.l_lo * P.d.l_lo;
     const int L2 = P.d.L_h * P.d.L_h;
-    const int block = L2 <= 64 ? 64 : (L2 <= 256 ? 256 : 512);
+    // whole waves only: the (p, q) past the block (the largest p, the longest recursions)
+    // go to its first lanes, which hold the smallest p
+    const int block = std::max(64, std::min(512, L2 / 64 * 64));
     hipLaunchKernelGGL(coupling_kernel, dim3(n_lm), dim3(block), 0, s, f, A, P.d.L_f, P.d.L_h,
                        P.d.l_lo);
     return hipGetLastError();
