@@ -230,16 +230,6 @@ __device__ ThreeJ threej_two_sided(int j2, int j3, int m2, int m3, const double*
     return r;
 }
 
-// Writes the unnormalised sequence into an LDS row; the caller rescales it.
-struct RowSink {
-    double* row;
-    int jmin, jmax, jm_hi, jb_lo;
-    __device__ void fwd(int j, double v) { row[j - jmin] = v; jm_hi = j; }
-    __device__ void bwd(int j, double v) { row[j - jmin] = v; jb_lo = j; }
-    __device__ void rescale_fwd(double s) { for (int j = jmin; j <= jm_hi; ++j) row[j - jmin] *= s; }
-    __device__ void rescale_bwd(double s) { for (int j = jb_lo; j <= jmax; ++j) row[j - jmin] *= s; }
-};
-
 // Accumulates sum_j w_j F(j) with w_j = sqrt(2j+1) Z(j) f_j^{mp} for j < L_f.  Z(j) vanishes
 // where j + p + l is odd (the parity rule of (j p l; 0 0 0)); those terms are skipped.
 struct DotSink {
@@ -271,17 +261,40 @@ __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restri
     const int jbase = l - L_h + 1 > 1 ? l - L_h + 1 : 1;
     for (int i = threadIdx.x; i < 2 * L_h + 1; i += blockDim.x) invj[i] = 1.0 / (double)(jbase + i);
     __syncthreads();
-    // Z rows: sqrt(2j+1) (j p l; 0 0 0) for j in [|l-p|, l+p], row p at offset p*p.
-    for (int p = threadIdx.x; p < L_h; p += blockDim.x) {
-        RowSink rs;
-        rs.row = Z + p * p;
-        rs.jmin = l > p ? l - p : p - l;
-        rs.jmax = l + p;
-        rs.jm_hi = rs.jmin;
-        rs.jb_lo = rs.jmax;
-        const ThreeJ t = threej_two_sided(p, l, 0, 0, invj, jbase, rs);
-        for (int j = t.jmin; j <= t.jmax; ++j)
-            rs.row[j - t.jmin] *= (j <= t.jm ? t.scale : t.c * t.scale) * sqrt(2.0 * j + 1.0);
+    // Z rows: sqrt(2j+1) (j p l; 0 0 0) for j in [|l-p|, l+p], row p at offset p*p.  The
+    // symbol vanishes unless j + p + l is even; its closed form (the Racah formula with zero
+    // orders) gives the ratio of consecutive nonzero entries, at a = p + l - j,
+    // b = j + l - p, c = j + p - l, J = j + p + l:
+    //   Z(j + 2) / Z(j) = -sqrt(2 (b+1)(c+1)(J/2+1) a / ((b+2)(c+2)(J+3)(a-1))).
+    // One 32-lane group per row: lane i takes j = |l-p| + 2i, the ratios are multiplied
+    // along the lanes, then normalised by sum_j (2j+1) Z^2 = 1 and signed by Z(|l-p|)'s sign
+    // (-1)^max(l, p).
+    {
+        const int grp = threadIdx.x >> 5, gl = threadIdx.x & 31, ngrp = blockDim.x >> 5;
+        for (int p = grp; p < L_h; p += ngrp) {
+            const int n = (l < p ? l : p) + 1;                 // nonzero entries (<= 32)
+            const int j0 = l > p ? l - p : p - l;
+            const int j = j0 + 2 * gl;
+            double R = 1.0;
+            if (gl >= 1 && gl < n) {
+                const double jp = j - 2;
+                const double a = p + l - jp, b = jp + l - p, c = jp + p - l, J = jp + p + l;
+                R = -sqrt(2.0 * (b + 1) * (c + 1) * (0.5 * J + 1) * a /
+                          ((b + 2) * (c + 2) * (J + 3) * (a - 1)));
+            }
+            for (int d = 1; d < 32; d <<= 1) {                 // inclusive prefix product
+                const double o = __shfl_up(R, d, 32);
+                if (gl >= d) R *= o;
+            }
+            double w = gl < n ? (2.0 * j + 1.0) * R * R : 0.0;
+            for (int d = 16; d > 0; d >>= 1) w += __shfl_xor(w, d, 32);
+            const double scale = (((l > p ? l : p) & 1) ? -1.0 : 1.0) / sqrt(w);
+            double* row = Z + p * p;
+            if (gl < n) {
+                row[2 * gl] = scale * R * sqrt(2.0 * j + 1.0);
+                if (gl + 1 < n) row[2 * gl + 1] = 0.0;
+            }
+        }
     }
     __syncthreads();
     const double sm = (m & 1) ? -1.0 : 1.0;
