@@ -230,33 +230,42 @@ __device__ ThreeJ threej_two_sided(int j2, int j3, int m2, int m3, const double*
     return r;
 }
 
-// Accumulates sum_j w_j F(j) with w_j = sqrt(2j+1) Z(j) f_j^{mp} for j < L_f.  Z(j) vanishes
-// where j + p + l is odd (the parity rule of (j p l; 0 0 0)); those terms are skipped.
+// Accumulates sum_j w_j F(j) f_j^{mp} and sum_j w_j F(j) f_j^{-mp} (the mirrored orders) with
+// w_j = sqrt(2j+1) Z(j) for j < L_f.  Z(j) vanishes where j + p + l is odd (the parity rule of
+// (j p l; 0 0 0)); those terms are skipped.
 struct DotSink {
     const double2* f;
     const double* z;     // Z row for this p: sqrt(2j+1) (j p l; 0 0 0) at index j - zlo
     int zlo, L_f, mp, par;
-    double fr, fi, br, bi;
-    __device__ void add(int j, double v, double& ar, double& ai) {
+    double fr, fi, br, bi;   // order mp: forward and backward sums
+    double gr, gi, cr, ci;   // order -mp
+    __device__ void add(int j, double v, double& ar, double& ai, double& xr, double& xi) {
         if (j >= L_f || ((j ^ par) & 1)) return;
         const double w = z[j - zlo] * v;
-        const double2 c = f[(int64_t)j * j + j + mp];
+        const int64_t c0 = (int64_t)j * j + j;
+        const double2 c = f[c0 + mp];
+        const double2 d = f[c0 - mp];
         ar += w * c.x;
         ai += w * c.y;
+        xr += w * d.x;
+        xi += w * d.y;
     }
-    __device__ void fwd(int j, double v) { add(j, v, fr, fi); }
-    __device__ void bwd(int j, double v) { add(j, v, br, bi); }
-    __device__ void rescale_fwd(double s) { fr *= s; fi *= s; }
-    __device__ void rescale_bwd(double s) { br *= s; bi *= s; }
+    __device__ void fwd(int j, double v) { add(j, v, fr, fi, gr, gi); }
+    __device__ void bwd(int j, double v) { add(j, v, br, bi, cr, ci); }
+    __device__ void rescale_fwd(double s) { fr *= s; fi *= s; gr *= s; gi *= s; }
+    __device__ void rescale_bwd(double s) { br *= s; bi *= s; cr *= s; ci *= s; }
 };
 
+// One block per (l, m >= 0).  (j p l; m-q q -m) and (j p l; q-m -q m) differ by (-1)^(j+p+l),
+// which is 1 wherever (j p l; 0 0 0) is nonzero, so A^p_q(l, m) and A^p_{-q}(l, -m) share
+// their 3j recursion and differ only in the f_j^{+-(m-q)} they sum.  For m = 0 the pairs
+// (p, q), (p, -q) share one recursion in the same way.
 __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restrict__ A, int L_f,
                                 int L_h, int l_lo) {
     __shared__ double Z[SLSHT_MAX_LH * SLSHT_MAX_LH];
     __shared__ double invj[2 * SLSHT_MAX_LH + 1];
-    const int lm = blockIdx.x;
-    int l, m;
-    lm_of(lm + l_lo * l_lo, l, m);
+    const Item it = item_decode(blockIdx.x, l_lo, 1);
+    const int l = it.l, m = it.m, L2 = L_h * L_h;
     // every recursion below runs over j in [|l - p|, l + p], p < L_h
     const int jbase = l - L_h + 1 > 1 ? l - L_h + 1 : 1;
     for (int i = threadIdx.x; i < 2 * L_h + 1; i += blockDim.x) invj[i] = 1.0 / (double)(jbase + i);
@@ -299,9 +308,18 @@ __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restri
     __syncthreads();
     const double sm = (m & 1) ? -1.0 : 1.0;
     const double pref = sm * sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
-    for (int pq = threadIdx.x; pq < L_h * L_h; pq += blockDim.x) {
+    // tasks: every (p, q) for m > 0; (p, q >= 0) for m = 0, task p(p+1)/2 + q
+    const int ntask = m > 0 ? L2 : L_h * (L_h + 1) / 2;
+    for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
         int p, q;
-        lm_of(pq, p, q);
+        if (m > 0) {
+            lm_of(task, p, q);
+        } else {
+            p = (int)((sqrt(8.0 * task + 1.0) - 1.0) * 0.5);
+            while ((p + 1) * (p + 2) / 2 <= task) ++p;
+            while (p * (p + 1) / 2 > task) --p;
+            q = task - p * (p + 1) / 2;
+        }
         DotSink ds;
         ds.f = f;
         ds.z = Z + p * p;
@@ -310,22 +328,27 @@ __global__ void coupling_kernel(const double2* __restrict__ f, double2* __restri
         ds.mp = m - q;
         ds.par = (p + l) & 1;
         ds.fr = ds.fi = ds.br = ds.bi = 0.0;
+        ds.gr = ds.gi = ds.cr = ds.ci = 0.0;
         const ThreeJ t = threej_two_sided(p, l, q, -m, invj, jbase, ds);
         const double k = pref * sqrt(2.0 * p + 1.0) * t.scale;
-        double2 out;
-        out.x = k * (ds.fr + t.c * ds.br);
-        out.y = k * (ds.fi + t.c * ds.bi);
-        A[(int64_t)lm * L_h * L_h + pq] = out;
+        const double2 out = vmk<double2>(k * (ds.fr + t.c * ds.br), k * (ds.fi + t.c * ds.bi));
+        const double2 mir = vmk<double2>(k * (ds.gr + t.c * ds.cr), k * (ds.gi + t.c * ds.ci));
+        A[(int64_t)it.lm * L2 + p * p + p + q] = out;
+        if (m > 0)
+            A[(int64_t)it.mirror * L2 + p * p + p - q] = mir;        // A^p_{-q}(l, -m)
+        else if (q > 0)
+            A[(int64_t)it.lm * L2 + p * p + p - q] = mir;            // A^p_{-q}(l, 0)
     }
 }
 
 hipError_t launch_coupling(const DevPlan& P, const double2* f, double2* A, hipStream_t s) {
-    const int n_lm = P.d.l_hi * P.d.l_hi - P.d.l_lo * P.d.l_lo;
+    // blocks: the (l, m >= 0)
+    const int n_blk = P.d.l_hi * (P.d.l_hi + 1) / 2 - P.d.l_lo * (P.d.l_lo + 1) / 2;
     const int L2 = P.d.L_h * P.d.L_h;
     // whole waves only: the (p, q) past the block (the largest p, the longest recursions)
     // go to its first lanes, which hold the smallest p
     const int block = std::max(64, std::min(512, L2 / 64 * 64));
-    hipLaunchKernelGGL(coupling_kernel, dim3(n_lm), dim3(block), 0, s, f, A, P.d.L_f, P.d.L_h,
+    hipLaunchKernelGGL(coupling_kernel, dim3(n_blk), dim3(block), 0, s, f, A, P.d.L_f, P.d.L_h,
                        P.d.l_lo);
     return hipGetLastError();
 }
