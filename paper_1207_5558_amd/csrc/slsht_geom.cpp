@@ -129,7 +129,7 @@ bool staged_geom(const slsht_desc& d, int n_theta_out, int n_items, StagedGeom& 
     // the last of the n_omega * n_theta_out columns' tiles carries padding.
     g.it = (size_t)16 * 16 * (2 * g.L + 1) * vb <= kWuMaxLds ? 16 : 8;
     g.lds = (size_t)g.it * 16 * (2 * g.L + 1) * vb;
-    g.threads = g.lds > 80 * 1024 ? 512 : 256;
+    g.threads = kWuThreads;
     g.n_itiles = ((n_items + g.it - 1) / g.it + 7) / 8 * 8;
     g.n_ctiles = g.ncol / 16;
     // column tiles per block: as many as keep >= 4096 blocks in the grid

@@ -203,6 +203,8 @@ size_t energy_lds_for(const DevPlan& P);
 // ENERGY output limits of the MFMA kernels (checked on the host).
 constexpr int kEnergyMaxOmega = 64;
 // omega samples of the W table (its twiddles sit in 16 KB of LDS beside the h d rows)
+constexpr int kWuThreads = 768;     // threads per block of the W/U kernel (12 waves)
+constexpr int kWuMaxWaves = 16;     // waves per block of the W/U kernel, at most
 constexpr int kWtableMaxOmega = 1024;
 // LDS of one W/U block's P|M rows (the CU has 160 KB; a few hundred bytes stay static)
 constexpr size_t kWuMaxLds = (size_t)156 << 10;

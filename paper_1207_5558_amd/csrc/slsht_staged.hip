@@ -190,23 +190,26 @@ __global__ void __launch_bounds__(64) staged_afrag_kernel(const double2* __restr
 //      in LDS (row = item * 16 + column: P_0..P_{L-1} at 0, M_0..M_{L-1} at L);
 //   2. the phi stage over those rows on the matrix cores (phi_stage_mfma), stored to g.
 // IT = 16 where the block's P|M rows fit in LDS (FP64 up to L_h = 19); else IT = 8: the A
-// operand's rows 8..15 are zero and the D rows past 8 are dropped.  Blocks whose P|M rows
-// take more than 80 KB run 8 waves (one block per CU), the others 4.
+// operand's rows 8..15 are zero and the D rows past 8 are dropped.  A block runs 12 waves
+// (one block per CU): the register cap of 168 VGPRs this sets costs the band-limit bucket 32
+// a few spilled registers, and still runs faster than 8 waves with none.
 // Blocks are laid out so that those sharing an item tile (the same A fragments) run on one
 // XCD: block b goes to XCD b mod 8 under round-robin dispatch.
 struct WUArgs {
     int L, n_omega, n_cols, ncol, n_theta_out, n_phi, nslot, l_lo, real_pair, n_items;
     int afrag_tile, n_itiles, n_ctiles, cchunk, n_cchunks;
-    uint32_t kmask[8];           // k of U_{+-k} taken by each wave (bit k)
+    uint32_t kmask[kWuMaxWaves];  // k of U_{+-k} taken by each wave (bit k)
 };
+
+static_assert(kWuThreads % 64 == 0 && kWuThreads / 64 <= kWuMaxWaves, "W/U block: whole waves, kmask sized");
 
 // Splits the k of U_{+-k} over `nw` waves: costliest first (MFMA steps in groups of 4,
 // four GEMMs, two for k = 0), each to the wave with the least work so far.
 static void wu_kmasks(int L, int nw, uint32_t* mask) {
     auto cost = [&](int k) { return ((u_steps(L, k) + 3) / 4) * (k ? 4 : 2); };
-    int load[8] = {0};
+    int load[kWuMaxWaves] = {0};
     bool used[SLSHT_MAX_LH] = {false};
-    for (int w = 0; w < 8; ++w) mask[w] = 0;
+    for (int w = 0; w < kWuMaxWaves; ++w) mask[w] = 0;
     for (int n = 0; n < L; ++n) {
         int k = -1;
         for (int c = 0; c < L; ++c)
@@ -227,8 +230,8 @@ __device__ __forceinline__ int afrag_off(int L, int k) {
     return off;
 }
 
-template <typename T, int LH, int IT>
-__global__ void __launch_bounds__(512) wu_phi_kernel(
+template <typename T, int LH, int IT, int NT>
+__global__ void __launch_bounds__(NT) wu_phi_kernel(
     const typename VecOf<T>::type* __restrict__ W, const T* __restrict__ af,
     const typename VecOf<T>::type* __restrict__ twphi, typename VecOf<T>::type* __restrict__ g,
     const WUArgs a) {
@@ -349,9 +352,10 @@ __global__ void __launch_bounds__(512) wu_phi_kernel(
 // ------------------------------------------------------------------------------
 // Host: launches.
 
-template <typename T, int LH, int IT>
+template <typename T, int LH, int IT, int NT>
 static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* W, const void* af,
                             void* g, hipStream_t s) {
+    if (sg.threads != NT) return hipErrorInvalidConfiguration;
     using V = typename VecOf<T>::type;
     WUArgs a;
     a.L = sg.L;
@@ -369,10 +373,10 @@ static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* 
     a.n_ctiles = sg.n_ctiles;
     a.cchunk = sg.cchunk;
     a.n_cchunks = sg.n_cchunks;
-    wu_kmasks(sg.L, sg.threads / 64, a.kmask);
+    wu_kmasks(sg.L, NT / 64, a.kmask);
     const int64_t nblk = (int64_t)sg.n_itiles * sg.n_cchunks;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const void* fn = (const void*)wu_phi_kernel<T, LH, IT>;
+    const void* fn = (const void*)wu_phi_kernel<T, LH, IT, NT>;
     if (sg.lds > 64 * 1024)
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sg.lds);
     const V* Wv = static_cast<const V*>(W);
@@ -380,7 +384,7 @@ static hipError_t launch_wu(const StagedGeom& sg, const DevPlan& P, const void* 
     const V* tw = static_cast<const V*>(P.T->tw_phi);
     V* gv = static_cast<V*>(g);
     void* args[] = {(void*)&Wv, (void*)&afv, (void*)&tw, (void*)&gv, (void*)&a};
-    return hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(sg.threads), args, sg.lds, s);
+    return hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(NT), args, sg.lds, s);
 }
 
 hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const double2* h, void* g,
@@ -403,15 +407,15 @@ hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const dou
                            (float*)af, sg, 0, sg.n_items);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // window band-limits 17..32 (staged_geom): buckets 24 and 32
+    // window band-limits 17..32 (staged_geom): buckets 24 and 32, blocks of kWuThreads
     const bool b24 = sg.L <= 24;
     if (sg.f64) {
-        if (sg.it == 16) return launch_wu<double, 24, 16>(sg, P, W, af, g, s);   // L_h <= 19
-        return b24 ? launch_wu<double, 24, 8>(sg, P, W, af, g, s)
-                   : launch_wu<double, 32, 8>(sg, P, W, af, g, s);
+        if (sg.it == 16) return launch_wu<double, 24, 16, kWuThreads>(sg, P, W, af, g, s);   // L_h <= 19
+        return b24 ? launch_wu<double, 24, 8, kWuThreads>(sg, P, W, af, g, s)
+                   : launch_wu<double, 32, 8, kWuThreads>(sg, P, W, af, g, s);
     }
-    return b24 ? launch_wu<float, 24, 16>(sg, P, W, af, g, s)
-               : launch_wu<float, 32, 16>(sg, P, W, af, g, s);
+    return b24 ? launch_wu<float, 24, 16, kWuThreads>(sg, P, W, af, g, s)
+               : launch_wu<float, 32, 16, kWuThreads>(sg, P, W, af, g, s);
 }
 
 }  // namespace slsht
