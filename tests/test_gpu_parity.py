@@ -81,6 +81,27 @@ def test_coupling_large_degrees():
     assert max_rel(A, ref) <= FP64_TOL
 
 
+@pytest.mark.parametrize("L_f,L_h,l_lo,l_hi", [
+    (12, 18, 0, 29),    # l < p: |l - p| ranges from both sides; 324 pairs: 320 lanes + 4 folded
+    (20, 9, 0, 12),     # 81 pairs: 64 lanes + 17 folded; m = 0 blocks pair (p, q) with (p, -q)
+    (30, 18, 41, 47),   # odd l_lo: (l, m >= 0) block numbering from an offset
+    (7, 1, 0, 7),       # scalar window: one pair, one Z row
+    (40, 32, 0, 3),     # 1024 pairs over 512 lanes, l < L_h for every row
+])
+def test_coupling_block_shapes_and_low_degrees(L_f, L_h, l_lo, l_hi):
+    """The coupling's block layouts against the oracle: one block per (l, m >= 0) writing
+    the orders +-m, Z rows from the closed-form ratio at l below and above p, whole-wave
+    blocks with the leftover (p, q) pairs folded onto the first lanes."""
+    rng = np.random.default_rng(L_f * 100 + L_h)
+    f = draw_coefficients(rng, L_f, 2.0, True)
+    announce(f"coupling L_f={L_f} L_h={L_h} l=[{l_lo},{l_hi})")
+    n_phi = 2 * (L_f + L_h) - 1
+    plan = api.Plan(api.make_desc(L_f, L_h, l_lo, l_hi, n_phi, (n_phi + 1) // 2, 2 * L_h - 1))
+    A = plan.coupling(dev(f)).cpu().numpy()
+    ref = oracle_coupling(f, L_f, L_h, l_lo, l_hi)
+    assert max_rel(A, ref) <= FP64_TOL
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
 def test_mid_sampled_rotations(mid_case, prec, tol):
     wl, f, h, idx, ref = mid_case
