@@ -372,12 +372,42 @@ __global__ void __launch_bounds__(256) inverse_kernel(const V* __restrict__ g,
     __syncthreads();
     const int64_t n = (int64_t)n_omega * n_theta * n_phi;
     const V* gp = g + (int64_t)lm * n;
+    // element i sits at phi index a of a row whose theta index is b; both advance with the
+    // block stride (sa, sb, with a carry from a into b), so the loop divides nothing
+    const int stride = blockDim.x;
+    const int sa = stride % n_phi, sb = (stride / n_phi) % n_theta;
+    int a = threadIdx.x % n_phi, b = (threadIdx.x / n_phi) % n_theta;
+    auto advance = [&]() {
+        a += sa;
+        b += sb;
+        if (a >= n_phi) {
+            a -= n_phi;
+            ++b;
+        }
+        if (b >= n_theta) b -= n_theta;
+    };
     double ar = 0.0, ai = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const int b = (int)((i / n_phi) % n_theta);
+    int64_t i = threadIdx.x;
+    for (; i + 3 * (int64_t)stride < n; i += 4 * (int64_t)stride) {   // four loads in flight
+        V v[4];
+        int bb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = gp[i + u * (int64_t)stride];
+            bb[u] = b;
+            advance();
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ar += qs[bb[u]] * (double)v[u].x;
+            ai += qs[bb[u]] * (double)v[u].y;
+        }
+    }
+    for (; i < n; i += stride) {
         const V v = gp[i];
         ar += qs[b] * (double)v.x;
         ai += qs[b] * (double)v.y;
+        advance();
     }
     for (int o = 32; o > 0; o >>= 1) {
         ar += __shfl_xor(ar, o);
