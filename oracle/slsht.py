@@ -16,7 +16,8 @@ Because Y_l^m(theta, phi) = lam_l^m(theta) e^{i m phi}, each sum over the grid
 is written as a sum over theta of a sum over phi; the sums are finite, so this
 is the same number.
 
-Also here, by the same quadrature:
+Also here, by the same quadrature (and, entry by entry, from sympy's exact Gaunt
+coefficients: oracle_coupling_exact):
   * A^p_q(l, m) = int f Y_p^q conj(Y_l^m) ds, the coefficient that the harmonic
     formulation contracts with the window (eq. Eq:harmonic_formulation with the
     triple product T; it equals conj((conj(f) Y_l^m)_p^q) of
@@ -184,6 +185,24 @@ def oracle_coupling(f, L_f, L_h, l_lo, l_hi):
             Y = S.lam_h[p, q + L_h - 1][:, None] * S.e_q[q + L_h - 1][None, :]
             out[:, p * p + p + q] = S.project((S.F * Y)[None])[0]
     return out
+
+
+def oracle_coupling_exact(f, L_f, l, m, p, q) -> complex:
+    """One coefficient A^p_q(l, m) = int f Y_p^q conj(Y_l^m) ds from exact integrals:
+    sum over l' of f_{l'}^{m-q} times int Y_{l'}^{m-q} Y_p^q conj(Y_l^m) ds, the integral
+    written as (-1)^m times the Gaunt coefficient G(l', p, l; m-q, q, -m)
+    (conj(Y_l^m) = (-1)^m Y_l^{-m}), which sympy evaluates exactly; the triple product T of
+    eq. Eq:harmonic_formulation.  For high degrees, where the quadrature above carries more
+    rounding (about 1e-12 relative at l = 300-400); slow (sympy)."""
+    from sympy import N
+    from sympy.physics.wigner import gaunt
+    mp = m - q
+    s = 0j
+    for lp in range(max(abs(l - p), abs(mp)), min(l + p, L_f - 1) + 1):
+        G = gaunt(lp, p, l, mp, q, -m)
+        if G != 0:
+            s += complex(f[lp * lp + lp + mp]) * float(N(G, 30))
+    return (-1) ** m * s
 
 
 def oracle_energy(g: np.ndarray, l_lo: int, l_hi: int) -> np.ndarray:

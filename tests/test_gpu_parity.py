@@ -6,6 +6,8 @@ of rotations for every (l, m), in the launch configuration the benchmark
 times.  Bars: relative Frobenius error per degree <= 1e-12 for FP64 and
 <= 1e-5 for FP32-mixed.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -100,6 +102,31 @@ def test_coupling_block_shapes_and_low_degrees(L_f, L_h, l_lo, l_hi):
     A = plan.coupling(dev(f)).cpu().numpy()
     ref = oracle_coupling(f, L_f, L_h, l_lo, l_hi)
     assert max_rel(A, ref) <= FP64_TOL
+
+
+def test_coupling_high_degree_golden():
+    """Degrees 300 and 399 (L_h = 32 and 6) against sampled exact values (sympy's Gaunt
+    coefficients through oracle_coupling_exact) stored by
+    tests/golden/make_coupling_high_degree.py: long 3j recursions, Z rows of the
+    closed-form ratio far from l = p, recursion coefficients near 1e17 under the refined
+    reciprocal square root."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "coupling_high_degree.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    cases = {}
+    for r in rows:
+        key = tuple(int(x) for x in r[:4])
+        cases.setdefault(key, []).append((int(r[4]), int(r[5]), int(r[6]),
+                                          complex(float(r[7]), float(r[8]))))
+    assert len(cases) == 2 and len(rows) == 512
+    for (L_f, L_h, seed, l), ents in cases.items():
+        announce(f"coupling golden L_f={L_f} L_h={L_h} l={l}")
+        f = draw_coefficients(np.random.default_rng(seed), L_f, 2.0, True)
+        K = 2 * L_h - 1
+        plan = api.Plan(api.make_desc(L_f, L_h, l, l + 1, K, L_h, K))
+        A = plan.coupling(dev(f)).cpu().numpy()
+        got = np.array([A[m + l, p * p + p + q] for m, p, q, _ in ents])
+        ref = np.array([v for *_, v in ents])
+        assert np.abs(got - ref).max() <= FP64_TOL * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])

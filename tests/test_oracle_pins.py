@@ -17,8 +17,8 @@ from sympy.physics.wigner import gaunt, wigner_d_small
 
 from oracle import grid as og
 from oracle.sph import legendre_table, sph_harm, synthesize
-from oracle.slsht import (oracle_coupling, oracle_energy, oracle_g, oracle_g_full,
-                          oracle_inverse, oracle_marginal, quadrature)
+from oracle.slsht import (oracle_coupling, oracle_coupling_exact, oracle_energy, oracle_g,
+                          oracle_g_full, oracle_inverse, oracle_marginal, quadrature)
 from oracle.wigner import delta_matrix, rotate_coefficients, wigner_D, wigner_d
 from paper_1207_5558_amd.inputs import draw_coefficients, draw_window, make_inputs, workload
 
@@ -308,6 +308,21 @@ def test_coupling_matches_exact_gaunt():
                     for lp in range(abs(mp), L_f):
                         s += f[lp * lp + lp + mp] * (-1) ** m * float(gaunt(lp, p, l, mp, q, -m))
                     assert abs(A[l * l + l + m, p * p + p + q] - s) < 1e-14
+
+
+def test_exact_coupling_entry():
+    """oracle_coupling_exact: equal to the quadrature route at small degrees, and for p = 0
+    (Y_0^0 = 1/sqrt(4 pi)) to f_l^m / sqrt(4 pi) at any degree."""
+    L_f, L_h = 5, 3
+    f, _ = _tiny_inputs(L_f, L_h, 21)
+    A = oracle_coupling(f, L_f, L_h, 0, 7)
+    for l, m, p, q in [(0, 0, 0, 0), (3, -2, 2, 1), (5, 4, 1, 1), (6, -6, 2, -2), (4, 0, 2, 0)]:
+        assert abs(oracle_coupling_exact(f, L_f, l, m, p, q) - A[l * l + l + m, p * p + p + q]) < 1e-14
+    rng = np.random.default_rng(4)
+    fb = draw_coefficients(rng, 300, 2.0, True)
+    for l, m in [(299, -299), (250, 17), (123, 0)]:
+        v = oracle_coupling_exact(fb, 300, l, m, 0, 0)
+        assert abs(v - fb[l * l + l + m] / np.sqrt(4 * np.pi)) < 1e-15 * abs(fb[l * l + l + m])
 
 
 def test_z_rotation_equivariance_on_grid():
