@@ -145,23 +145,30 @@ hipError_t launch_wtable(const void* dtab, bool d64, const double2* h, void* W, 
 }
 
 // ------------------------------------------------------------------------------
+// offset (in 64-lane fragment steps) of U_{+k}'s A fragments within a 16-item tile
+__device__ __forceinline__ int afrag_off(int L, int k) {
+    int off = 0;
+    for (int j = 0; j < k; ++j) off += (j ? 2 : 1) * u_steps(L, j);
+    return off;
+}
+
 // A fragments of one chunk of items: tile `tile` covers items item0 + 16 tile + i; step s of
 // U_{+-k} holds, in lane (i, j4), component (j4 & 1) of A^p_{+-k} with p = k + 2s + (j4 >> 1).
-// Items past the chunk are zero.
+// Items past the chunk are zero.  kAfragWaves waves per tile take the k in turn.
+constexpr int kAfragWaves = 4;
 template <typename T>
-__global__ void __launch_bounds__(64) staged_afrag_kernel(const double2* __restrict__ A,
-                                                          T* __restrict__ af, const StagedGeom g,
-                                                          int item0, int n_chunk) {
-    const int tile = blockIdx.x, lane = threadIdx.x;
+__global__ void __launch_bounds__(64 * kAfragWaves) staged_afrag_kernel(
+    const double2* __restrict__ A, T* __restrict__ af, const StagedGeom g, int item0, int n_chunk) {
+    const int tile = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = tile * 16 + (lane & 15), j4 = lane >> 4;
     const int L = g.L;
     const bool valid = row < n_chunk;
     int64_t lm = 0;
     if (valid) lm = item_decode(item0 + row, g.l_lo, g.real_pair).lm;
     T* out = af + (int64_t)tile * g.afrag_tile + lane;
-    int off = 0;
-    for (int k = 0; k < L; ++k) {
+    for (int k = wave; k < L; k += kAfragWaves) {
         const int steps = u_steps(L, k);
+        int off = afrag_off(L, k);
         for (int sg = 0; sg < (k ? 2 : 1); ++sg) {
             const int q = sg ? -k : k;
             for (int s = 0; s < steps; ++s) {
@@ -201,7 +208,8 @@ struct WUArgs {
     uint32_t kmask[kWuMaxWaves];  // k of U_{+-k} taken by each wave (bit k)
 };
 
-static_assert(kWuThreads % 64 == 0 && kWuThreads / 64 <= kWuMaxWaves, "W/U block: whole waves, kmask sized");
+static_assert(kWuThreads % 64 == 0 && kWuThreads / 64 <= kWuMaxWaves,
+              "W/U block: whole waves, kmask sized");
 
 // Splits the k of U_{+-k} over `nw` waves: costliest first (MFMA steps in groups of 4,
 // four GEMMs, two for k = 0), each to the wave with the least work so far.
@@ -221,13 +229,6 @@ static void wu_kmasks(int L, int nw, uint32_t* mask) {
         load[best] += cost(k);
         mask[best] |= 1u << k;
     }
-}
-
-// offset (in 64-lane fragment steps) of U_{+k}'s A fragments within a 16-item tile
-__device__ __forceinline__ int afrag_off(int L, int k) {
-    int off = 0;
-    for (int j = 0; j < k; ++j) off += (j ? 2 : 1) * u_steps(L, j);
-    return off;
 }
 
 template <typename T, int LH, int IT, int NT>
@@ -399,11 +400,12 @@ hipError_t launch_synthesis_staged(const DevPlan& P, const double2* A, const dou
     hipError_t e = launch_wtable(P.T->dtab, sg.f64 != 0, h, W, sg.f64 != 0, sg.L, sg.N,
                                  sg.n_omega, sg.n_theta_out, lay, s);
     if (e != hipSuccess) return e;
+    const dim3 ablk(64 * kAfragWaves);
     if (sg.f64)
-        hipLaunchKernelGGL(staged_afrag_kernel<double>, dim3(sg.ntiles), dim3(64), 0, s, A,
+        hipLaunchKernelGGL(staged_afrag_kernel<double>, dim3(sg.ntiles), ablk, 0, s, A,
                            (double*)af, sg, 0, sg.n_items);
     else
-        hipLaunchKernelGGL(staged_afrag_kernel<float>, dim3(sg.ntiles), dim3(64), 0, s, A,
+        hipLaunchKernelGGL(staged_afrag_kernel<float>, dim3(sg.ntiles), ablk, 0, s, A,
                            (float*)af, sg, 0, sg.n_items);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
