@@ -107,9 +107,12 @@ __device__ __forceinline__ void load_phi_b(const typename VecOf<T>::type* __rest
 // at 0.., M_0..M_{L-1} at moff..).  Work unit = (8 complex rows, 64 slots): four 16-slot
 // GEMM tiles share the unit's A fragments (tiles wholly past nslot are skipped); their
 // results are transposed across lane groups so that lane l holds slot 64 unit + l of each
-// row and every store instruction writes consecutive outputs of one row.  The waves of the
-// block split the units, slot-range-major, so that a wave's B fragments (cos/sin(k phi_s))
-// stay in registers while it walks the rows of one slot range.
+// row and every store instruction writes consecutive outputs of one row.  Rows of at most
+// 32 slots (short rows: n_phi <= 63) take two 8-row groups per unit instead, tiles 0-1 for
+// the first and 2-3 for the second, so that after the transpose lanes 0-31 hold slots 0-31
+// of the first group and lanes 32-63 those of the second, and one store instruction writes
+// two rows.  The waves of the block split the units, slot-range-major, so that a wave's B
+// fragments (cos/sin(k phi_s)) stay in registers while it walks the rows of one slot range.
 //   row_out(r, out, mirror, msign): destination of row r (out = nullptr skips it) and, with
 //   conjugate symmetry, the row of order -m (g(l,-m) = (-1)^m conj(g(l,m))) or nullptr.
 template <typename T, int LH, typename RowOut>
@@ -125,6 +128,7 @@ __device__ __forceinline__ void phi_stage_mfma(const typename VecOf<T>::type* PM
     const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
     const int li = lane & 15, lj = lane >> 4;
     const int n_rt = (nrows + 7) / 8;
+    const bool pair = nslot <= 32;               // two 8-row groups per unit
     const int n_st = (nslot + 63) / 64;
     const int kq = (L + 3) / 4;
     const int arow = MF::row_of(li), apart = MF::part_of(li);
@@ -133,37 +137,43 @@ __device__ __forceinline__ void phi_stage_mfma(const typename VecOf<T>::type* PM
     constexpr int NB = kKeepB ? 4 : 1;
     T bcr[NB][KQ], bsr[NB][KQ];
     int cur_st = -1;
-    const int nu = n_rt * n_st;
+    const int nu = pair ? (n_rt + 1) / 2 : n_rt * n_st;
     const int u_end = ((wave + 1) * nu) / nwaves;
     for (int u = (wave * nu) / nwaves; u < u_end; ++u) {
-        const int st = u / n_rt;
-        const int rt = u - st * n_rt;
-        const int ntile = min(4, (nslot - st * 64 + 15) / 16);   // tiles holding slots
+        const int st = pair ? 0 : u / n_rt;
+        const int rt = pair ? 2 * u : u - st * n_rt;          // the (first) 8-row group
+        // tiles holding slots: of the 64-slot range, or of each 32-slot half in pair mode
+        const int ntile = pair ? (nslot + 15) / 16 : min(4, (nslot - st * 64 + 15) / 16);
         if (kKeepB && st != cur_st) {
             cur_st = st;
 #pragma unroll
             for (int x = 0; x < NB; ++x) load_phi_b<T, KQ>(twp, nslot, L, kq, st * 64 + x * 16 + li, lj,
                                                          bcr[x], bsr[x]);
         }
-        const int ra = rt * 8 + arow;
-        const T* prow = reinterpret_cast<const T*>(PM + (ra < nrows ? ra : 0) * pms) + apart;
         T pa[KQ], ma[KQ];
-#pragma unroll
-        for (int kk = 0; kk < KQ; ++kk) {
-            const int k = 4 * kk + lj;
-            const bool ok = kk < kq && k < L && ra < nrows;
-            pa[kk] = ok ? prow[2 * k] : T(0);
-            ma[kk] = ok ? prow[2 * (moff + k)] : T(0);
-        }
         // w[x][e]: x = 16-slot tile of the unit, e = (row h, value): Re/Im of C+S, C-S
         T w[4][8];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-            const int xb = kKeepB ? x : 0;
+            // pair mode: tiles 2-3 repeat the slots of tiles 0-1 for the second row group
+            const int tx = pair ? (x & 1) : x;
+            const int rg = pair ? rt + (x >> 1) : rt;
+            if (x == 0 || (pair && x == 2)) {
+                const int ra = rg * 8 + arow;
+                const T* prow = reinterpret_cast<const T*>(PM + (ra < nrows ? ra : 0) * pms) + apart;
+#pragma unroll
+                for (int kk = 0; kk < KQ; ++kk) {
+                    const int k = 4 * kk + lj;
+                    const bool ok = kk < kq && k < L && ra < nrows;
+                    pa[kk] = ok ? prow[2 * k] : T(0);
+                    ma[kk] = ok ? prow[2 * (moff + k)] : T(0);
+                }
+            }
+            const int xb = kKeepB ? tx : 0;
             Acc C = {0, 0, 0, 0}, Sg = {0, 0, 0, 0};
-            if (x < ntile) {
+            if (tx < ntile && rg < n_rt) {
                 if (!kKeepB)
-                    load_phi_b<T, KQ>(twp, nslot, L, kq, st * 64 + x * 16 + li, lj, bcr[0], bsr[0]);
+                    load_phi_b<T, KQ>(twp, nslot, L, kq, st * 64 + tx * 16 + li, lj, bcr[0], bsr[0]);
                 const T* bc = bcr[xb];
                 const T* bs = bsr[xb];
 #pragma unroll
@@ -184,14 +194,16 @@ __device__ __forceinline__ void phi_stage_mfma(const typename VecOf<T>::type* PM
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) transpose4(w[0][e], w[1][e], w[2][e], w[3][e]);
-        // now w[j][e] of lane l belongs to row group j, slot 64*st + l
-        const int s = st * 64 + lane;
+        // now w[j][e] of lane l belongs to row group j and slot 64*st + l, or in pair mode
+        // to row group j of 8-row group rt + (l >> 5) and slot l & 31
+        const int s = pair ? (lane & 31) : st * 64 + lane;
+        const int rbase = (pair ? rt + (lane >> 5) : rt) * 8;
         if (s >= nslot) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int rr = rt * 8 + (h ? MF::second_row(j) : MF::first_row(j));
+                const int rr = rbase + (h ? MF::second_row(j) : MF::first_row(j));
                 if (rr >= nrows) continue;
                 V* out;
                 V* mout;
