@@ -211,10 +211,10 @@ struct WUArgs {
 static_assert(kWuThreads % 64 == 0 && kWuThreads / 64 <= kWuMaxWaves,
               "W/U block: whole waves, kmask sized");
 
-// Splits the k of U_{+-k} over `nw` waves: costliest first (MFMA steps in groups of 4,
-// four GEMMs, two for k = 0), each to the wave with the least work so far.
+// Splits the k of U_{+-k} over `nw` waves: costliest first (MFMA steps, four GEMMs, two
+// for k = 0), each to the wave with the least work so far.
 static void wu_kmasks(int L, int nw, uint32_t* mask) {
-    auto cost = [&](int k) { return ((u_steps(L, k) + 3) / 4) * (k ? 4 : 2); };
+    auto cost = [&](int k) { return u_steps(L, k) * (k ? 4 : 2); };
     int load[kWuMaxWaves] = {0};
     bool used[SLSHT_MAX_LH] = {false};
     for (int w = 0; w < kWuMaxWaves; ++w) mask[w] = 0;
@@ -312,6 +312,7 @@ __global__ void __launch_bounds__(NT) wu_phi_kernel(
                 }
 #pragma unroll
                 for (int u = 0; u < SB; ++u) {
+                    if (s0 + u >= steps) break;          // the last group's padding (uniform)
                     upr = MF::step(ap[u], (j4 & 1) ? -wp[u].y : wp[u].x, upr);
                     upi = MF::step(ap[u], (j4 & 1) ? wp[u].x : wp[u].y, upi);
                     if (k) {
